@@ -1,0 +1,188 @@
+"""Python binding of the FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark import
+this module.  The product path (the HIP library and its binding) never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rok4e_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CXXFLAGS = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+            "-shared", "-fPIC"]
+
+JVP_FD, JVP_COMPLEX, JVP_EXACT = 0, 1, 2
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with g++ (always recompiles)."""
+    cmd = ["g++", *CXXFLAGS, "-o", _LIB, _SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+class OrcMech(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("W", C.c_void_p), ("cp", C.c_void_p), ("hf", C.c_void_p),
+                ("reac", C.c_void_p), ("prod", C.c_void_p),
+                ("lnAf", C.c_void_p), ("bf", C.c_void_p), ("Ef", C.c_void_p),
+                ("lnAr", C.c_void_p), ("br", C.c_void_p), ("Er", C.c_void_p)]
+
+
+class OrcOpts(C.Structure):
+    _fields_ = [("M", C.c_int32), ("jvp", C.c_int32), ("fixed_steps", C.c_int32),
+                ("max_attempts", C.c_int32), ("eps_fd", C.c_double), ("h0", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = C.CDLL(_LIB)
+    return _lib
+
+
+def _p(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+class MechHandle:
+    """Keeps contiguous copies of the mechanism arrays alive for the C struct."""
+
+    def __init__(self, mech):
+        self.arrays = dict(
+            W=np.ascontiguousarray(mech.W, np.float64), cp=np.ascontiguousarray(mech.cp, np.float64),
+            hf=np.ascontiguousarray(mech.hf, np.float64),
+            reac=np.ascontiguousarray(mech.reac, np.int32).reshape(-1),
+            prod=np.ascontiguousarray(mech.prod, np.int32).reshape(-1),
+            lnAf=np.ascontiguousarray(mech.lnAf, np.float64), bf=np.ascontiguousarray(mech.bf, np.float64),
+            Ef=np.ascontiguousarray(mech.Ef, np.float64), lnAr=np.ascontiguousarray(mech.lnAr, np.float64),
+            br=np.ascontiguousarray(mech.br, np.float64), Er=np.ascontiguousarray(mech.Er, np.float64))
+        self.n_species = int(mech.n_species)
+        self.n_reactions = int(mech.n_reactions)
+        self.s = OrcMech(self.n_species, self.n_reactions,
+                         *[self.arrays[k].ctypes.data for k in
+                           ("W", "cp", "hf", "reac", "prod", "lnAf", "bf", "Ef", "lnAr", "br", "Er")])
+
+
+def coefficients() -> dict:
+    out = np.zeros(21)
+    lib().orc_coefficients(_p(out), 21)
+    names = ["gamma", "g21", "g31", "g32", "g41", "g42", "g43", "a21", "a31", "a32", "a41",
+             "a42", "a43", "b1", "b2", "b3", "b4", "bh1", "bh2", "bh3", "bh4"]
+    return dict(zip(names, out.tolist()))
+
+
+def rhs(mech, Y, T, p, S=None):
+    """f(u) for every cell; Y [ns, n], T [n], p [n], S [(ns+1), n] or None."""
+    h = MechHandle(mech)
+    Y = np.ascontiguousarray(Y, np.float64)
+    T = np.ascontiguousarray(T, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    n = T.shape[0]
+    dY = np.zeros_like(Y)
+    dT = np.zeros_like(T)
+    S = None if S is None else np.ascontiguousarray(S, np.float64)
+    lib().orc_rhs(C.byref(h.s), C.c_int64(n), _p(Y), _p(T), _p(p), _p(S), _p(dY), _p(dT))
+    return dY, dT
+
+
+def cell_jvp(mech, u, p, v, mode=JVP_FD, eps_fd=0.0):
+    h = MechHandle(mech)
+    u = np.ascontiguousarray(u, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    out = np.zeros_like(u)
+    rc = lib().orc_cell_jvp(C.byref(h.s), _p(u), C.c_double(p), _p(v), C.c_int(mode),
+                            C.c_double(eps_fd), _p(out))
+    if rc != 0:
+        raise RuntimeError("jvp mode not available")
+    return out
+
+
+def cell_arnoldi(mech, u, p, M, mode=JVP_FD, eps_fd=0.0):
+    h = MechHandle(mech)
+    u = np.ascontiguousarray(u, np.float64)
+    n = u.shape[0]
+    Q = np.zeros((M, n))
+    H = np.zeros((M, M))
+    meff = lib().orc_cell_arnoldi(C.byref(h.s), _p(u), C.c_double(p), C.c_int(M), C.c_int(mode),
+                                  C.c_double(eps_fd), _p(Q), _p(H))
+    return Q.T.copy(), H, meff
+
+
+def make_opts(M, jvp=JVP_FD, fixed_steps=0, max_attempts=0, eps_fd=0.0, h0=0.0):
+    return OrcOpts(int(M), int(jvp), int(fixed_steps), int(max_attempts), float(eps_fd), float(h0))
+
+
+def integrate(mech, Y, T, p, dt, rtol, atol, M, S=None, jvp=JVP_FD, fixed_steps=0,
+              max_attempts=0, eps_fd=0.0, h0=0.0, nthreads=0):
+    """Integrate every cell over [0, dt]; returns (Y, T, accepted, rejected, status)
+    as new arrays (inputs untouched)."""
+    h = MechHandle(mech)
+    Y = np.array(Y, np.float64, order="C", copy=True)
+    T = np.array(T, np.float64, copy=True)
+    p = np.ascontiguousarray(p, np.float64)
+    S = None if S is None else np.ascontiguousarray(S, np.float64)
+    n = T.shape[0]
+    acc = np.zeros(n, np.int32)
+    rej = np.zeros(n, np.int32)
+    st = np.zeros(n, np.int32)
+    o = make_opts(M, jvp, fixed_steps, max_attempts, eps_fd, h0)
+    lib().orc_integrate(C.byref(h.s), C.byref(o), C.c_int64(n), _p(Y), _p(T), _p(p), _p(S),
+                        C.c_double(dt), C.c_double(rtol), C.c_double(atol), _p(acc), _p(rej),
+                        _p(st), C.c_int(nthreads))
+    return Y, T, acc, rej, st
+
+
+def integrate_linear(A, c, u, dt, rtol, atol, M, jvp=JVP_EXACT, fixed_steps=0, max_attempts=0,
+                     h0=0.0, trace_cap=0):
+    """ROK4E on u' = A u + c.  Returns (u, accepted, rejected, status) and, when
+    ``trace_cap`` > 0, a fifth item: the [attempts, 4] trace (t, h, err, accepted)."""
+    A = np.ascontiguousarray(A, np.float64)
+    n = A.shape[0]
+    c = None if c is None else np.ascontiguousarray(c, np.float64)
+    u = np.array(u, np.float64, copy=True)
+    acc, rej, st, ntr = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    o = make_opts(M, jvp, fixed_steps, max_attempts, 0.0, h0)
+    tr = np.zeros((max(trace_cap, 1), 4))
+    lib().orc_integrate_linear(C.c_int(n), _p(A), _p(c), C.byref(o), _p(u), C.c_double(dt),
+                               C.c_double(rtol), C.c_double(atol), C.byref(acc), C.byref(rej),
+                               C.byref(st), _p(tr) if trace_cap > 0 else None, C.c_int(trace_cap),
+                               C.byref(ntr))
+    if trace_cap > 0:
+        return u, acc.value, rej.value, st.value, tr[:min(ntr.value, trace_cap)].copy()
+    return u, acc.value, rej.value, st.value
+
+
+def row_dense_linear(A, c, u, dt, nsteps, jvp=JVP_EXACT):
+    A = np.ascontiguousarray(A, np.float64)
+    c = None if c is None else np.ascontiguousarray(c, np.float64)
+    u = np.array(u, np.float64, copy=True)
+    rc = lib().orc_row_dense_linear(C.c_int(A.shape[0]), _p(A), _p(c), _p(u), C.c_double(dt),
+                                    C.c_int(nsteps), C.c_int(jvp))
+    if rc != 0:
+        raise RuntimeError(f"row_dense_linear failed: {rc}")
+    return u
+
+
+def row_dense_cell(mech, u, p, dt, nsteps, jvp=JVP_COMPLEX):
+    h = MechHandle(mech)
+    u = np.array(u, np.float64, copy=True)
+    rc = lib().orc_row_dense_cell(C.byref(h.s), _p(u), C.c_double(p), C.c_double(dt),
+                                  C.c_int(nsteps), C.c_int(jvp))
+    if rc != 0:
+        raise RuntimeError(f"row_dense_cell failed: {rc}")
+    return u

@@ -1,0 +1,657 @@
+// FP64 CPU oracle for the batched ROK4E reaction substep.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, scalar reference that the
+// HIP path is checked against.  Only the test suite, the smoke check and the CPU
+// baseline leg of the benchmark may load it.  It shares no code, header, table or
+// helper with the HIP library; both sides get their inputs from the seeded generator.
+//
+// What is computed (paper: Wu, Ma & Ihme, "Efficient time stepping for reactive
+// turbulent simulations with stiff chemistry"):
+//   * the right-hand side of the adiabatic 0-D reactor, Sec. 4.4 eq. e:cv_reactor,
+//     read as a constant-pressure reactor (c_p with h_k) with mass-action rates;
+//   * the matrix-free finite-difference Jacobian-vector product, Sec. 4.3;
+//   * the Arnoldi process giving Q_n and the Hessenberg H_n = Q_n^T J_n Q_n,
+//     Sec. 4.1 eq. e:jac_proj (modified Gram-Schmidt);
+//   * the four stages in the transformed form, Sec. 4.3 eq. e:s_stage_row_transformed,
+//     with (I - h gamma A_n)^{-1} applied through the twice-used Woodbury identity,
+//     eq. e:solve_kry_jac;
+//   * the embedded error estimate and the PI step-size controller, Sec. 4.3;
+//   * the integration loop of Algorithm a:ROK4E.
+// Where the paper is silent or garbled the readings are:
+//   - coefficient table t:coeff_rok4e: the b row reads (b1, b2, b3, b4) =
+//     (0.1943.., 0.4831.., 0, 0.3224..) and the b-hat row (.., .., 0.1865.., 0);
+//   - the ROW form e:s_stage_row carries h in front of A_n sum gamma_ij k_j;
+//   - error norm: weighted RMS over all N components with scale atol + rtol |u*_i|;
+//   - err_n = 1 before the first accepted step; err_n is updated on accept only;
+//   - the last step is clipped to the interval end;
+//   - FD increment delta = sqrt(eps (1 + ||u_n||_2)) for unit-norm Arnoldi vectors;
+//   - Arnoldi: M_eff = min(M, N); stop early when the new vector's norm falls below
+//     1e-12 of the norm before orthogonalisation; ||f_n|| = 0 gives M_eff = 0;
+//   - after a rejected step the basis of the same u_n is reused (identical result);
+//   - non-finite u* or err counts as a rejection with err = +inf.
+//
+// Built with -O2 -fno-fast-math -ffp-contract=off so each operation rounds once.
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <type_traits>
+#include <vector>
+#include <omp.h>
+
+namespace {
+
+using cplx = std::complex<double>;
+
+constexpr double kRu = 8.314462618;      // J/(mol K)
+constexpr double kTref = 298.15;         // K
+
+// ROK4E coefficients, table t:coeff_rok4e (row labels read as stated above).
+constexpr double G = 0.572816062482135;
+constexpr double G21 = -0.602765307997356;
+constexpr double G31 = -1.389195789724843, G32 = 1.072950969011413;
+constexpr double G41 = 0.992356412977094, G42 = -1.390032613873701, G43 = -0.440875890223325;
+constexpr double A21 = 0.432364435748567;
+constexpr double A31 = -0.514211316876170, A32 = 1.382271144617360;
+constexpr double A41 = -0.514211316876170, A42 = 1.382271144617360, A43 = 0.0;
+constexpr double B1 = 0.194335256262729, B2 = 0.483167813989227, B3 = 0.0, B4 = 0.322496929748044;
+constexpr double BH1 = -0.217819895945721, BH2 = 1.03130847478467, BH3 = 0.186511421161047, BH4 = 0.0;
+
+}  // namespace
+
+extern "C" {
+
+typedef struct {
+  int32_t n_species, n_reactions;
+  const double *W, *cp, *hf;              // [ns]: kg/mol, J/(kg K), J/kg
+  const int32_t *reac, *prod;             // [nr*2], -1 where absent
+  const double *lnAf, *bf, *Ef, *lnAr, *br, *Er;   // [nr]; A in cm-mol-s, E in J/mol
+} orc_mech;
+
+typedef struct {
+  int32_t M;             // Krylov dimension
+  int32_t jvp;           // 0 finite difference, 1 complex step, 2 exact (linear problems)
+  int32_t fixed_steps;   // 0 adaptive, n > 0: n equal steps without error control
+  int32_t max_attempts;  // attempts allowed per cell (<= 0: 1000000)
+  double eps_fd;         // unit roundoff used in the FD increment (<= 0: 2^-52)
+  double h0;             // first trial step (<= 0: dt)
+} orc_opts;
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------- problems ----
+
+// One 0-D reactor cell: u = (Y_1..Y_ns, T), constant pressure p, optional constant
+// forcing s (length ns+1) added to f.
+struct CellProblem {
+  static constexpr bool kComplex = true;
+  const orc_mech* m;
+  double p;
+  const double* s;   // may be null
+  int n() const { return m->n_species + 1; }
+
+  template <class S>
+  void f(const S* u, S* out) const {
+    const int ns = m->n_species, nr = m->n_reactions;
+    const S T = u[ns];
+    S sigma = 0.0, cpbar = 0.0;
+    for (int k = 0; k < ns; ++k) sigma += u[k] / m->W[k];
+    for (int k = 0; k < ns; ++k) cpbar += u[k] * m->cp[k];
+    const S rho = p / (kRu * T * sigma);                       // kg/m^3
+    std::vector<S> c(ns), wdot(ns, S(0.0));
+    for (int k = 0; k < ns; ++k) c[k] = 1e-6 * rho * u[k] / m->W[k];   // mol/cm^3
+    const S lnT = std::log(T);
+    const S invRT = 1.0 / (kRu * T);
+    for (int j = 0; j < nr; ++j) {
+      const S kf = std::exp(m->lnAf[j] + m->bf[j] * lnT - m->Ef[j] * invRT);
+      const S kr = std::exp(m->lnAr[j] + m->br[j] * lnT - m->Er[j] * invRT);
+      S pf = 1.0, pr = 1.0;
+      for (int a = 0; a < 2; ++a) {
+        if (m->reac[2 * j + a] >= 0) pf = pf * c[m->reac[2 * j + a]];
+        if (m->prod[2 * j + a] >= 0) pr = pr * c[m->prod[2 * j + a]];
+      }
+      const S q = kf * pf - kr * pr;                            // mol/(cm^3 s)
+      // omega_k += nu_kj q_j with the net coefficient nu_kj (products - reactants),
+      // added once per distinct species of reaction j, reactions in index order.
+      int sp[4], nu[4], nsp = 0;
+      for (int a = 0; a < 2; ++a) {
+        const int r = m->reac[2 * j + a];
+        if (r < 0) continue;
+        int i = 0;
+        while (i < nsp && sp[i] != r) ++i;
+        if (i == nsp) { sp[nsp] = r; nu[nsp] = 0; ++nsp; }
+        nu[i] -= 1;
+      }
+      for (int a = 0; a < 2; ++a) {
+        const int r = m->prod[2 * j + a];
+        if (r < 0) continue;
+        int i = 0;
+        while (i < nsp && sp[i] != r) ++i;
+        if (i == nsp) { sp[nsp] = r; nu[nsp] = 0; ++nsp; }
+        nu[i] += 1;
+      }
+      for (int i = 0; i < nsp; ++i) wdot[sp[i]] += static_cast<double>(nu[i]) * q;
+    }
+    S hsum = 0.0;
+    for (int k = 0; k < ns; ++k) {
+      const S w = 1e6 * wdot[k];                                // mol/(m^3 s)
+      out[k] = m->W[k] * w / rho;
+      const S hk = m->hf[k] + m->cp[k] * (T - kTref);
+      hsum += hk * m->W[k] * w;
+    }
+    out[ns] = -hsum / (rho * cpbar);
+    if (s)
+      for (int k = 0; k <= ns; ++k) out[k] += s[k];
+  }
+};
+
+// Linear test problem f(u) = A u + c (A row-major n x n).
+struct LinearProblem {
+  static constexpr bool kComplex = true;
+  int nn;
+  const double* A;
+  const double* c;
+  int n() const { return nn; }
+  template <class S>
+  void f(const S* u, S* out) const {
+    for (int i = 0; i < nn; ++i) {
+      S acc = c ? S(c[i]) : S(0.0);
+      for (int j = 0; j < nn; ++j) acc += A[i * nn + j] * u[j];
+      out[i] = acc;
+    }
+  }
+  void exact_jvp(const double* v, double* out) const {
+    for (int i = 0; i < nn; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < nn; ++j) acc += A[i * nn + j] * v[j];
+      out[i] = acc;
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" {
+// Right-hand side supplied by the caller: out = f(u), u and out of length n.
+typedef void (*orc_rhs_fn)(int n, const double* u, double* out, void* ctx);
+}
+
+namespace {
+
+// A caller-supplied f (finite-difference Jacobian-vector products only).
+struct CallbackProblem {
+  static constexpr bool kComplex = false;
+  int nn;
+  orc_rhs_fn fn;
+  void* ctx;
+  int n() const { return nn; }
+  template <class S>
+  void f(const S* u, S* out) const {
+    if constexpr (std::is_same<S, double>::value) fn(nn, u, out, ctx);
+  }
+};
+
+double norm2(const std::vector<double>& x) {
+  double s = 0.0;
+  for (double v : x) s += v * v;
+  return std::sqrt(s);
+}
+
+double dot(const double* a, const double* b, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+// Jacobian-vector product J(u) v in the selected mode.  fu = f(u).
+template <class P>
+bool jvp(const P& prob, int mode, double eps_fd, const std::vector<double>& u,
+         const std::vector<double>& fu, const double* v, double* out) {
+  const int n = prob.n();
+  if (mode == 0) {
+    // Finite difference, Sec. 4.3: (f(u + delta v) - f(u)) / delta.
+    const double delta = std::sqrt(eps_fd * (1.0 + norm2(u)));
+    std::vector<double> up(n), fp(n);
+    for (int i = 0; i < n; ++i) up[i] = u[i] + delta * v[i];
+    prob.template f<double>(up.data(), fp.data());
+    for (int i = 0; i < n; ++i) out[i] = (fp[i] - fu[i]) / delta;
+    return true;
+  }
+  if (mode == 1 && P::kComplex) {
+    // Complex step: Im f(u + i eps v) / eps, exact to roundoff for analytic f.
+    const double eps = 1e-30;
+    std::vector<cplx> uc(n), fc(n);
+    for (int i = 0; i < n; ++i) uc[i] = cplx(u[i], eps * v[i]);
+    prob.template f<cplx>(uc.data(), fc.data());
+    for (int i = 0; i < n; ++i) out[i] = fc[i].imag() / eps;
+    return true;
+  }
+  if constexpr (std::is_same<P, LinearProblem>::value) {
+    if (mode == 2) {
+      prob.exact_jvp(v, out);
+      return true;
+    }
+  }
+  return false;
+}
+
+// Arnoldi with modified Gram-Schmidt, Sec. 4.1 (Q: n x M column-major, H: M x M
+// row-major).  Returns M_eff.
+template <class P>
+int arnoldi(const P& prob, int mode, double eps_fd, int M, const std::vector<double>& u,
+            const std::vector<double>& fu, std::vector<double>& Q, std::vector<double>& H) {
+  const int n = prob.n();
+  std::fill(Q.begin(), Q.end(), 0.0);
+  std::fill(H.begin(), H.end(), 0.0);
+  int Meff = M < n ? M : n;
+  const double beta = norm2(fu);
+  if (beta == 0.0) return 0;
+  for (int i = 0; i < n; ++i) Q[i] = fu[i] / beta;
+  std::vector<double> w(n);
+  for (int j = 0; j < Meff; ++j) {
+    if (!jvp(prob, mode, eps_fd, u, fu, &Q[j * n], w.data())) return -1;
+    const double wnorm0 = norm2(w);
+    for (int i = 0; i <= j; ++i) {
+      const double hij = dot(&Q[i * n], w.data(), n);
+      H[i * M + j] = hij;
+      for (int r = 0; r < n; ++r) w[r] -= hij * Q[i * n + r];
+    }
+    if (j + 1 < Meff) {
+      const double hn = norm2(w);
+      if (!(hn > 1e-12 * wnorm0)) return j + 1;     // breakdown: invariant subspace
+      H[(j + 1) * M + j] = hn;
+      for (int r = 0; r < n; ++r) Q[(j + 1) * n + r] = w[r] / hn;
+    }
+  }
+  return Meff;
+}
+
+// Dense LU with partial pivoting of an m x m row-major matrix (in place).
+bool lu_factor(std::vector<double>& a, int m, std::vector<int>& piv) {
+  piv.resize(m);
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int i = k + 1; i < m; ++i)
+      if (std::fabs(a[i * m + k]) > std::fabs(a[p * m + k])) p = i;
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < m; ++j) std::swap(a[k * m + j], a[p * m + j]);
+    if (a[k * m + k] == 0.0) return false;
+    for (int i = k + 1; i < m; ++i) {
+      const double l = a[i * m + k] / a[k * m + k];
+      a[i * m + k] = l;
+      for (int j = k + 1; j < m; ++j) a[i * m + j] -= l * a[k * m + j];
+    }
+  }
+  return true;
+}
+
+// Solves (P A) x = P b with the factors of lu_factor: whole rows were swapped there, so
+// all row interchanges are applied to b first, then unit-lower and upper substitution.
+void lu_solve(const std::vector<double>& a, int m, const std::vector<int>& piv, double* x) {
+  for (int k = 0; k < m; ++k)
+    if (piv[k] != k) std::swap(x[k], x[piv[k]]);
+  for (int k = 0; k < m; ++k)
+    for (int i = k + 1; i < m; ++i) x[i] -= a[i * m + k] * x[k];
+  for (int i = m - 1; i >= 0; --i) {
+    double s = x[i];
+    for (int j = i + 1; j < m; ++j) s -= a[i * m + j] * x[j];
+    x[i] = s / a[i * m + i];
+  }
+}
+
+struct Result {
+  int status = 0;       // 0 ok, 1 attempt limit, 2 step underflow, 3 bad input, 4 bad mode
+  int accepted = 0;
+  int rejected = 0;
+};
+
+// Optional per-attempt record: (t at the start of the attempt, h, err, accepted).
+struct Trace {
+  double* buf = nullptr;
+  int cap = 0;
+  int n = 0;
+  void add(double t, double h, double err, bool acc) {
+    if (n < cap) {
+      buf[4 * n + 0] = t; buf[4 * n + 1] = h; buf[4 * n + 2] = err; buf[4 * n + 3] = acc ? 1.0 : 0.0;
+    }
+    ++n;
+  }
+};
+
+bool all_finite(const std::vector<double>& x) {
+  for (double v : x)
+    if (!std::isfinite(v)) return false;
+  return true;
+}
+
+// One cell: Algorithm a:ROK4E over [0, dt].  u is overwritten with the state at dt
+// (or at the last accepted time on failure).
+template <class P>
+Result rok4e_one(const P& prob, std::vector<double>& u, double dt, double rtol, double atol,
+                 const orc_opts& o, Trace* trace = nullptr) {
+  Result res;
+  const int n = prob.n();
+  const int M = o.M;
+  const double eps_fd = o.eps_fd > 0.0 ? o.eps_fd : std::ldexp(1.0, -52);
+  const int max_att = o.max_attempts > 0 ? o.max_attempts : 1000000;
+  std::vector<double> fn(n), Q(static_cast<size_t>(n) * M), H(static_cast<size_t>(M) * M);
+  std::vector<double> k1(n), k2(n), k3(n), k4(n), F(n), arg(n), fs(n), ustar(n), e(n);
+  std::vector<double> L, z(M), y(M);
+  std::vector<int> piv;
+  int Meff = 0;
+  bool basis_valid = false;
+
+  double t = 0.0;
+  double h = o.h0 > 0.0 ? o.h0 : dt;
+  double err_prev = 1.0;
+  int attempts = 0;
+  const bool fixed = o.fixed_steps > 0;
+  if (fixed) h = dt / o.fixed_steps;
+  int steps_done = 0;
+
+  // Applies k = F - Q (z - y) - sum_j (gamma_ij / gamma) k_j with y = (I - h gamma H)^{-1} z,
+  // z = Q^T F (Algorithm a:ROK4E, stage update).
+  auto stage_solve = [&](const std::vector<double>& Fi, std::vector<double>& ki,
+                         const std::vector<double>& corr) {
+    for (int i = 0; i < Meff; ++i) z[i] = dot(&Q[i * n], Fi.data(), n);
+    for (int i = 0; i < Meff; ++i) y[i] = z[i];
+    if (Meff > 0) lu_solve(L, Meff, piv, y.data());
+    for (int r = 0; r < n; ++r) {
+      double qw = 0.0;
+      for (int i = 0; i < Meff; ++i) qw += Q[i * n + r] * (z[i] - y[i]);
+      ki[r] = Fi[r] - qw - corr[r];
+    }
+  };
+
+  std::vector<double> corr(n);
+  while (fixed ? steps_done < o.fixed_steps : t < dt) {
+    if (attempts >= max_att) { res.status = 1; break; }
+    bool last = false;
+    if (!fixed && h >= (dt - t) * (1.0 - 1e-12)) { h = dt - t; last = true; }
+
+    if (!basis_valid) {
+      prob.template f<double>(u.data(), fn.data());
+      Meff = arnoldi(prob, o.jvp, eps_fd, M, u, fn, Q, H);
+      if (Meff < 0) { res.status = 4; return res; }
+      basis_valid = true;
+    }
+    // L = I - h gamma H (M_eff x M_eff), factored once per attempt.
+    L.assign(static_cast<size_t>(Meff) * Meff, 0.0);
+    for (int i = 0; i < Meff; ++i)
+      for (int j = 0; j < Meff; ++j)
+        L[i * Meff + j] = (i == j ? 1.0 : 0.0) - h * G * H[i * M + j];
+    if (Meff > 0 && !lu_factor(L, Meff, piv)) {
+      // Singular projected matrix: treat as a failed (rejected) attempt.
+      ++attempts; ++res.rejected;
+      h *= 0.2;
+      if (h < 16.0 * std::numeric_limits<double>::epsilon() * dt) { res.status = 2; break; }
+      continue;
+    }
+    // Stage 1: F1 = f_n.
+    std::fill(corr.begin(), corr.end(), 0.0);
+    stage_solve(fn, k1, corr);
+    // Stage 2: F2 = f(u + h a21 k1) + (g21/g) k1.
+    for (int r = 0; r < n; ++r) arg[r] = u[r] + h * (A21 * k1[r]);
+    prob.template f<double>(arg.data(), fs.data());
+    for (int r = 0; r < n; ++r) corr[r] = (G21 / G) * k1[r];
+    for (int r = 0; r < n; ++r) F[r] = fs[r] + corr[r];
+    stage_solve(F, k2, corr);
+    // Stage 3: F3 = f(u + h(a31 k1 + a32 k2)) + (g31 k1 + g32 k2)/g.
+    for (int r = 0; r < n; ++r) arg[r] = u[r] + h * (A31 * k1[r] + A32 * k2[r]);
+    prob.template f<double>(arg.data(), fs.data());
+    for (int r = 0; r < n; ++r) corr[r] = (G31 * k1[r] + G32 * k2[r]) / G;
+    for (int r = 0; r < n; ++r) F[r] = fs[r] + corr[r];
+    stage_solve(F, k3, corr);
+    // Stage 4 reuses f of stage 3: a41 = a31, a42 = a32, a43 = 0.
+    for (int r = 0; r < n; ++r) corr[r] = (G41 * k1[r] + G42 * k2[r] + G43 * k3[r]) / G;
+    for (int r = 0; r < n; ++r) F[r] = fs[r] + corr[r];
+    stage_solve(F, k4, corr);
+
+    for (int r = 0; r < n; ++r)
+      ustar[r] = u[r] + h * (B1 * k1[r] + B2 * k2[r] + B3 * k3[r] + B4 * k4[r]);
+    ++attempts;
+    if (fixed) {
+      u = ustar;
+      ++res.accepted;
+      ++steps_done;
+      basis_valid = false;
+      continue;
+    }
+    // Embedded error e = u_hat - u* = h sum_j (bh_j - b_j) k_j, weighted RMS norm.
+    double ss = 0.0;
+    for (int r = 0; r < n; ++r) {
+      e[r] = h * ((BH1 - B1) * k1[r] + (BH2 - B2) * k2[r] + (BH3 - B3) * k3[r] + (BH4 - B4) * k4[r]);
+      const double sc = atol + rtol * std::fabs(ustar[r]);
+      const double ratio = e[r] / sc;
+      ss += ratio * ratio;
+    }
+    double err = std::sqrt(ss / n);
+    if (!std::isfinite(err) || !all_finite(ustar)) err = std::numeric_limits<double>::infinity();
+    // PI controller: alpha = 0.7/4, beta = 0.4/4.
+    const double fac = std::fmin(5.0, std::fmax(0.2, 0.8 * std::pow(std::fmax(err_prev, 1e-10), 0.1) /
+                                                     std::pow(std::fmax(err, 1e-10), 0.175)));
+    const double hstar = h * fac;
+    if (trace) trace->add(t, h, err, err <= 1.0);
+    if (err <= 1.0) {
+      u = ustar;
+      t = last ? dt : t + h;
+      err_prev = err;
+      h = hstar;
+      ++res.accepted;
+      basis_valid = false;
+    } else {
+      h = hstar;
+      ++res.rejected;
+    }
+    if (t < dt && h < 16.0 * std::numeric_limits<double>::epsilon() * dt) { res.status = 2; break; }
+  }
+  return res;
+}
+
+// Dense Rosenbrock (ROW) step with the full Jacobian assembled column by column from
+// the same JVP mode: the classical ROW method e:s_stage_row with A_n = J_n,
+// fixed steps, used to check that M = N reduces ROK4E to it.
+template <class P>
+int row_dense(const P& prob, std::vector<double>& u, double dt, int nsteps, int mode, double eps_fd) {
+  const int n = prob.n();
+  const double h = dt / nsteps;
+  std::vector<double> fn(n), J(static_cast<size_t>(n) * n), col(n), ev(n), L;
+  std::vector<double> k[4] = {std::vector<double>(n), std::vector<double>(n), std::vector<double>(n),
+                              std::vector<double>(n)};
+  std::vector<double> arg(n), fs(n), F(n), corr(n);
+  std::vector<int> piv;
+  const double gam[4][4] = {{0, 0, 0, 0}, {G21, 0, 0, 0}, {G31, G32, 0, 0}, {G41, G42, G43, 0}};
+  for (int step = 0; step < nsteps; ++step) {
+    prob.template f<double>(u.data(), fn.data());
+    for (int c = 0; c < n; ++c) {
+      std::fill(ev.begin(), ev.end(), 0.0);
+      ev[c] = 1.0;
+      if (!jvp(prob, mode, eps_fd, u, fn, ev.data(), col.data())) return -1;
+      for (int r = 0; r < n; ++r) J[r * n + c] = col[r];
+    }
+    L.assign(static_cast<size_t>(n) * n, 0.0);
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) L[r * n + c] = (r == c ? 1.0 : 0.0) - h * G * J[r * n + c];
+    if (!lu_factor(L, n, piv)) return -2;
+    for (int i = 0; i < 4; ++i) {
+      if (i == 0) {
+        fs = fn;
+      } else if (i == 1) {
+        for (int r = 0; r < n; ++r) arg[r] = u[r] + h * (A21 * k[0][r]);
+        prob.template f<double>(arg.data(), fs.data());
+      } else if (i == 2) {
+        for (int r = 0; r < n; ++r) arg[r] = u[r] + h * (A31 * k[0][r] + A32 * k[1][r]);
+        prob.template f<double>(arg.data(), fs.data());
+      }  // i == 3 reuses fs of stage 3
+      for (int r = 0; r < n; ++r) {
+        double cr = 0.0;
+        for (int j = 0; j < i; ++j) cr += gam[i][j] * k[j][r];
+        corr[r] = cr / G;
+        F[r] = fs[r] + corr[r];
+      }
+      lu_solve(L, n, piv, F.data());
+      for (int r = 0; r < n; ++r) k[i][r] = F[r] - corr[r];
+    }
+    for (int r = 0; r < n; ++r)
+      u[r] = u[r] + h * (B1 * k[0][r] + B2 * k[1][r] + B3 * k[2][r] + B4 * k[3][r]);
+  }
+  return 0;
+}
+
+bool cell_input_ok(const orc_mech* m, const double* Y, const double* T, const double* p,
+                   int64_t n, int64_t c) {
+  for (int k = 0; k < m->n_species; ++k)
+    if (!std::isfinite(Y[k * n + c])) return false;
+  return std::isfinite(T[c]) && T[c] > 0.0 && std::isfinite(p[c]) && p[c] > 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Coefficients in the order gamma, g21, g31, g32, g41, g42, g43, a21, a31, a32, a41,
+// a42, a43, b1..b4, bh1..bh4 (21 values).
+int orc_coefficients(double* out, int n) {
+  const double c[21] = {G, G21, G31, G32, G41, G42, G43, A21, A31, A32, A41, A42, A43,
+                        B1, B2, B3, B4, BH1, BH2, BH3, BH4};
+  if (n < 21) return -1;
+  std::memcpy(out, c, sizeof c);
+  return 21;
+}
+
+// Right-hand side for n cells in the structure-of-arrays layout (Y[k*n + c]).
+// S (optional) is the forcing [(ns+1) * n], same layout with T last.
+int orc_rhs(const orc_mech* m, int64_t n, const double* Y, const double* T, const double* p,
+            const double* S, double* dY, double* dT) {
+  const int ns = m->n_species;
+  for (int64_t c = 0; c < n; ++c) {
+    std::vector<double> u(ns + 1), f(ns + 1), s;
+    for (int k = 0; k < ns; ++k) u[k] = Y[k * n + c];
+    u[ns] = T[c];
+    if (S) {
+      s.resize(ns + 1);
+      for (int k = 0; k <= ns; ++k) s[k] = S[k * n + c];
+    }
+    CellProblem prob{m, p[c], S ? s.data() : nullptr};
+    prob.f<double>(u.data(), f.data());
+    for (int k = 0; k < ns; ++k) dY[k * n + c] = f[k];
+    dT[c] = f[ns];
+  }
+  return 0;
+}
+
+// Jacobian-vector product of one cell: out = J(u) v in the given mode (u and v of
+// length ns+1).
+int orc_cell_jvp(const orc_mech* m, const double* u, double p, const double* v, int mode,
+                 double eps_fd, double* out) {
+  const int n = m->n_species + 1;
+  CellProblem prob{m, p, nullptr};
+  std::vector<double> uu(u, u + n), fu(n);
+  prob.f<double>(uu.data(), fu.data());
+  return jvp(prob, mode, eps_fd > 0 ? eps_fd : std::ldexp(1.0, -52), uu, fu, v, out) ? 0 : -1;
+}
+
+// Arnoldi basis of one cell.  Q is n x M (column j at Q[j*n]), H is M x M row-major.
+int orc_cell_arnoldi(const orc_mech* m, const double* u, double p, int M, int mode,
+                     double eps_fd, double* Q, double* H) {
+  const int n = m->n_species + 1;
+  CellProblem prob{m, p, nullptr};
+  std::vector<double> uu(u, u + n), fu(n), QQ(static_cast<size_t>(n) * M), HH(static_cast<size_t>(M) * M);
+  prob.f<double>(uu.data(), fu.data());
+  const int Meff = arnoldi(prob, mode, eps_fd > 0 ? eps_fd : std::ldexp(1.0, -52), M, uu, fu, QQ, HH);
+  std::memcpy(Q, QQ.data(), QQ.size() * sizeof(double));
+  std::memcpy(H, HH.data(), HH.size() * sizeof(double));
+  return Meff;
+}
+
+// Integrates n cells over [0, dt] in place.  acc/rej/status may be null.
+int orc_integrate(const orc_mech* m, const orc_opts* o, int64_t n, double* Y, double* T,
+                  const double* p, const double* S, double dt, double rtol, double atol,
+                  int32_t* acc, int32_t* rej, int32_t* status, int nthreads) {
+  const int ns = m->n_species;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  for (int64_t c = 0; c < n; ++c) {
+    Result r;
+    if (!cell_input_ok(m, Y, T, p, n, c)) {
+      r.status = 3;
+    } else {
+      std::vector<double> u(ns + 1), s;
+      for (int k = 0; k < ns; ++k) u[k] = Y[k * n + c];
+      u[ns] = T[c];
+      if (S) {
+        s.resize(ns + 1);
+        for (int k = 0; k <= ns; ++k) s[k] = S[k * n + c];
+      }
+      CellProblem prob{m, p[c], S ? s.data() : nullptr};
+      r = rok4e_one(prob, u, dt, rtol, atol, *o);
+      for (int k = 0; k < ns; ++k) Y[k * n + c] = u[k];
+      T[c] = u[ns];
+    }
+    if (acc) acc[c] = r.accepted;
+    if (rej) rej[c] = r.rejected;
+    if (status) status[c] = r.status;
+  }
+  return 0;
+}
+
+// ROK4E on the linear problem u' = A u + c (A row-major n x n), u in place.
+// trace (optional, 4 doubles per attempt, up to trace_cap attempts) records t, h, err
+// and the accept flag of each adaptive attempt; *n_trace receives the attempt count.
+int orc_integrate_linear(int n, const double* A, const double* c, const orc_opts* o, double* u,
+                         double dt, double rtol, double atol, int32_t* acc, int32_t* rej,
+                         int32_t* status, double* trace, int trace_cap, int32_t* n_trace) {
+  LinearProblem prob{n, A, c};
+  std::vector<double> uu(u, u + n);
+  Trace tr;
+  tr.buf = trace;
+  tr.cap = trace ? trace_cap : 0;
+  Result r = rok4e_one(prob, uu, dt, rtol, atol, *o, &tr);
+  if (n_trace) *n_trace = tr.n;
+  std::memcpy(u, uu.data(), n * sizeof(double));
+  if (acc) *acc = r.accepted;
+  if (rej) *rej = r.rejected;
+  if (status) *status = r.status;
+  return 0;
+}
+
+// ROK4E on a caller-supplied autonomous system u' = f(u) (finite-difference JVPs).
+int orc_integrate_callback(int n, orc_rhs_fn fn, void* ctx, const orc_opts* o, double* u,
+                           double dt, double rtol, double atol, int32_t* acc, int32_t* rej,
+                           int32_t* status) {
+  CallbackProblem prob{n, fn, ctx};
+  std::vector<double> uu(u, u + n);
+  Result r = rok4e_one(prob, uu, dt, rtol, atol, *o);
+  std::memcpy(u, uu.data(), n * sizeof(double));
+  if (acc) *acc = r.accepted;
+  if (rej) *rej = r.rejected;
+  if (status) *status = r.status;
+  return 0;
+}
+
+// Dense ROW with the full Jacobian, fixed steps, on the linear problem.
+int orc_row_dense_linear(int n, const double* A, const double* c, double* u, double dt, int nsteps,
+                         int mode) {
+  LinearProblem prob{n, A, c};
+  std::vector<double> uu(u, u + n);
+  const int rc = row_dense(prob, uu, dt, nsteps, mode, std::ldexp(1.0, -52));
+  std::memcpy(u, uu.data(), n * sizeof(double));
+  return rc;
+}
+
+// Dense ROW with the full Jacobian, fixed steps, on one reactor cell (u of length ns+1).
+int orc_row_dense_cell(const orc_mech* m, double* u, double p, double dt, int nsteps, int mode) {
+  CellProblem prob{m, p, nullptr};
+  const int n = m->n_species + 1;
+  std::vector<double> uu(u, u + n);
+  const int rc = row_dense(prob, uu, dt, nsteps, mode, std::ldexp(1.0, -52));
+  std::memcpy(u, uu.data(), n * sizeof(double));
+  return rc;
+}
+
+}  // extern "C"

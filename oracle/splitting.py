@@ -1,0 +1,64 @@
+"""Splitting drivers around the oracle's ROK4E (test infrastructure only).
+
+The Simpler balanced splitting, Sec. 3.3 eq. e:simpler_balanced, for a system
+u' = T(u) + R(u): with c_n = -T(u_n), integrate u' = R(u) - c_n over h with ROK4E
+(the stiff reaction substep), then u' = T(u) + c_n over h/2 with an explicit
+Runge-Kutta method (the non-stiff transport substep; the first transport half step of
+the balanced form is identically at rest and is dropped).  Strang splitting,
+e:strang_t1..e:strang_t3, is the control that does not preserve steady states.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import oracle as O
+
+_FN = C.CFUNCTYPE(None, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
+
+
+def rok4e(f, u0, h, rtol=1e-10, atol=1e-14, M=None):
+    """ROK4E (finite-difference JVPs) on u' = f(u) over [0, h]."""
+    u = np.array(u0, np.float64, copy=True)
+    n = u.shape[0]
+
+    def cb(nn, up, outp, ctx):
+        uu = np.ctypeslib.as_array(up, shape=(nn,))
+        out = np.ctypeslib.as_array(outp, shape=(nn,))
+        out[:] = f(uu.copy())
+
+    fn = _FN(cb)
+    acc, rej, st = C.c_int32(), C.c_int32(), C.c_int32()
+    o = O.make_opts(M if M is not None else n)
+    O.lib().orc_integrate_callback(C.c_int(n), fn, None, C.byref(o), O._p(u), C.c_double(h),
+                                   C.c_double(rtol), C.c_double(atol), C.byref(acc),
+                                   C.byref(rej), C.byref(st))
+    if st.value != 0:
+        raise RuntimeError(f"ROK4E substep failed with status {st.value}")
+    return u
+
+
+def rk4(f, u0, h, nsub=8):
+    """Classical 4th-order Runge-Kutta with nsub equal steps (transport substeps)."""
+    u = np.array(u0, np.float64, copy=True)
+    dt = h / nsub
+    for _ in range(nsub):
+        k1 = f(u)
+        k2 = f(u + 0.5 * dt * k1)
+        k3 = f(u + 0.5 * dt * k2)
+        k4 = f(u + dt * k3)
+        u = u + dt / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return u
+
+
+def simpler_step(T, R, u, h, reaction=rok4e, transport=rk4):
+    c = -T(u)                                            # c_n = -T(U_n)
+    u1 = reaction(lambda v: R(v) - c, u, h)              # reaction substep over h
+    return transport(lambda v: T(v) + c, u1, 0.5 * h)    # transport over h/2
+
+
+def strang_step(T, R, u, h, reaction=rok4e, transport=rk4):
+    u1 = transport(T, u, 0.5 * h)
+    u2 = reaction(R, u1, h)
+    return transport(T, u2, 0.5 * h)
