@@ -1,0 +1,163 @@
+/*
+ * rok4e.h -- C ABI of the batched ROK4E reaction substep on MI355X (gfx950).
+ *
+ * Every cell of a batch is an independent adiabatic 0-D reactor at constant pressure
+ * (the paper's reaction substep of the Simpler balanced splitting, Sec. 3.3
+ * eq. e:simpler_balanced, and the reactor model of Sec. 4.4 eq. e:cv_reactor, read with
+ * c_p and h_k).  Each cell integrates u = (Y_1..Y_ns, T) over [0, dt] with the
+ * four-stage Rosenbrock-Krylov method ROK4E (Sec. 4, Algorithm a:ROK4E): a Krylov
+ * basis of dimension M from finite-difference Jacobian-vector products (Sec. 4.3),
+ * the transformed stages e:s_stage_row_transformed with the projected solve
+ * e:solve_kry_jac, the embedded error estimate and the PI step-size controller.
+ *
+ * Conventions
+ *  - All state arrays are device pointers in the structure-of-arrays layout:
+ *    Y[k * n_cells + c] (species-major), T[c], p[c].  FP64 always.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    Calls that launch work are asynchronous on that stream.
+ *  - Return value: ROK4E_OK (0) or a negative ROK4E_E* code; rok4e_strerror() names it.
+ *    Argument errors are detected on the host before anything is launched.
+ *  - Per-cell outcomes cannot be known synchronously; they go to per-cell status
+ *    codes (ROK4E_CELL_*) readable through rok4e_cell_stats_ptr / rok4e_get_stats.
+ *  - Units: W kg/mol, cp J/(kg K), hf J/kg at 298.15 K, A in cm-mol-s (ln A given),
+ *    Ea J/mol, T K, p Pa, dt s.
+ */
+#ifndef ROK4E_H
+#define ROK4E_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define ROK4E_OK 0
+#define ROK4E_EINVAL (-1)    /* invalid argument (null pointer with n_cells > 0, sizes, tolerances, M) */
+#define ROK4E_ENOMEM (-2)    /* device allocation failed */
+#define ROK4E_EHIP (-3)      /* HIP runtime or launch error */
+#define ROK4E_ECAPTURE (-4)  /* workspace too small while the stream is being captured */
+#define ROK4E_ENOTSUP (-5)   /* no kernel variant for this (n_species, M, precision, layout) */
+
+/* Per-cell status codes. */
+#define ROK4E_CELL_OK 0
+#define ROK4E_CELL_MAX_ATTEMPTS 1  /* attempt limit reached before dt; state = last accepted */
+#define ROK4E_CELL_STEP_UNDERFLOW 2 /* step fell below 16 eps dt; state = last accepted */
+#define ROK4E_CELL_BAD_INPUT 3     /* non-finite Y/T/p, T <= 0 or p <= 0; state untouched */
+
+/* Precision of the right-hand side, Krylov basis and projected solve.  The state
+ * update, the finite-difference perturbation and difference, the error norm and
+ * the step controller are FP64 in both modes. */
+#define ROK4E_FP64 0
+#define ROK4E_MIXED 1
+
+/* Cell scheduling. */
+#define ROK4E_PERSISTENT 0   /* one launch; waves pull cells from a device work queue */
+#define ROK4E_PER_ATTEMPT 1  /* one launch per attempt over the still-active cells */
+
+typedef struct rok4e_mech rok4e_mech;   /* opaque handle */
+
+/* Mechanism description; host arrays, copied to the device by rok4e_mech_create. */
+typedef struct {
+  int32_t n_species;          /* ns >= 1 */
+  int32_t n_reactions;        /* nr >= 0 */
+  const double* W;            /* [ns] molecular weight */
+  const double* cp;           /* [ns] constant heat capacity */
+  const double* hf;           /* [ns] formation enthalpy at 298.15 K */
+  const int32_t* reac;        /* [nr * 2] reactant species of reaction j at 2j, 2j+1; -1 if absent */
+  const int32_t* prod;        /* [nr * 2] product species, same layout */
+  const double* lnAf;         /* [nr] ln of forward pre-exponential factor */
+  const double* bf;           /* [nr] forward temperature exponent */
+  const double* Ef;           /* [nr] forward activation energy */
+  const double* lnAr;         /* [nr] reverse triple, same meaning */
+  const double* br;
+  const double* Er;
+} rok4e_mech_desc;
+
+typedef struct {
+  int32_t M;              /* Krylov dimension, 1..16 (the method's implicitness; not tuned) */
+  int32_t precision;      /* ROK4E_FP64 or ROK4E_MIXED */
+  int32_t max_attempts;   /* attempts allowed per cell; <= 0 means 1000000 */
+  int32_t fixed_steps;    /* 0: adaptive; n > 0: n equal steps, no error control */
+  int32_t lanes_per_cell; /* 0: automatic; else 16, 32 or 64 (result-neutral) */
+  int32_t waves_per_block;/* 0: automatic; 1..4 waves of 64 lanes (result-neutral) */
+  int32_t blocks_per_cu;  /* 0: automatic; persistent-grid blocks per compute unit */
+  int32_t scheduling;     /* ROK4E_PERSISTENT or ROK4E_PER_ATTEMPT (result-neutral) */
+  double h0;              /* first trial step; <= 0 means dt */
+} rok4e_options;
+
+typedef struct {
+  int64_t n_cells;        /* cells of the last integrate call */
+  int64_t accepted;       /* accepted attempts, summed over cells */
+  int64_t rejected;       /* rejected attempts, summed over cells */
+  int64_t max_attempts;   /* largest accepted + rejected of any cell */
+  int64_t status_count[4];/* cells per ROK4E_CELL_* status */
+} rok4e_stats;
+
+/* Fills *o with the defaults (M = 4, FP64, automatic layout, persistent). */
+void rok4e_options_default(rok4e_options* o);
+
+/* Creates a handle on the current HIP device: validates the description (species
+ * indices in range, finite parameters, W > 0, cp > 0), builds the device tables
+ * (reaction parameters, species-major production lists) and selects the kernel
+ * variant.  o may be NULL (defaults).  The caller keeps ownership of d and o. */
+int rok4e_mech_create(const rok4e_mech_desc* d, const rok4e_options* o, rok4e_mech** out);
+
+/* Frees the handle and its device memory (synchronises the device). NULL is a no-op. */
+int rok4e_mech_destroy(rok4e_mech* m);
+
+/* Replaces the launch options (layout, waves, grid, scheduling, M, precision,
+ * max_attempts, fixed_steps, h0) of an existing handle. */
+int rok4e_set_options(rok4e_mech* m, const rok4e_options* o);
+int rok4e_get_options(const rok4e_mech* m, rok4e_options* o);
+
+/* Sizes the per-cell workspace for up to max_cells cells.  integrate grows the
+ * workspace on demand outside stream capture; inside a capture it returns
+ * ROK4E_ECAPTURE instead, so call this before capturing. */
+int rok4e_reserve(rok4e_mech* m, int64_t max_cells);
+
+/* Integrates n_cells cells in place over [0, dt] (Algorithm a:ROK4E with relative
+ * and absolute tolerances rtol > 0, atol >= 0).  Y, T are read and overwritten; p is
+ * read only and constant over the substep.  n_cells == 0 is a no-op. */
+int rok4e_integrate(int64_t n_cells, rok4e_mech* mech, double* Y, double* T, const double* p,
+                    double dt, double rtol, double atol, void* stream);
+
+/* As rok4e_integrate with a constant forcing added to f: S[(ns+1) * n_cells] in the
+ * state layout (T last), the balancing term T(U_n) of the Simpler balanced splitting
+ * (e:simpler_balanced: c_n = -T(U_n), reaction substep u' = R(u) - c_n).  S may be NULL. */
+int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* mech, double* Y, double* T,
+                           const double* p, const double* S, double dt, double rtol,
+                           double atol, void* stream);
+
+/* Evaluates the reactor right-hand side f(u) for every cell (Sec. 4.4, e:cv_reactor):
+ * dY[k * n_cells + c], dT[c].  Inputs are not modified. */
+int rok4e_rhs(int64_t n_cells, rok4e_mech* mech, const double* Y, const double* T, const double* p,
+              double* dY, double* dT, void* stream);
+
+/* Arnoldi process of Sec. 4.1 (e:jac_proj) at each cell's state, with the handle's M and
+ * precision: Q[(c * M + j) * (ns+1) + r] (column j of cell c), H[(c * M + i) * M + j],
+ * Meff[c].  Device output buffers sized by the caller.  For tests and diagnostics. */
+int rok4e_arnoldi(int64_t n_cells, rok4e_mech* mech, const double* Y, const double* T,
+                  const double* p, double* Q, double* H, int32_t* Meff, void* stream);
+
+/* Copies the summary of the last integrate call to the host (synchronises stream). */
+int rok4e_get_stats(rok4e_mech* m, rok4e_stats* out, void* stream);
+
+/* Device pointers to the per-cell accepted/rejected/status arrays of the last call
+ * (valid until the next reserve or destroy; owned by the handle). */
+int rok4e_cell_stats_ptr(rok4e_mech* m, const int32_t** acc, const int32_t** rej,
+                         const int32_t** status);
+
+/* Copies the per-cell accepted/rejected/status counts of the last call into caller
+ * buffers of n_cells int32 each (host or device pointers; any may be NULL), ordered on
+ * stream.  Does not synchronise. */
+int rok4e_copy_cell_stats(rok4e_mech* m, int32_t* acc, int32_t* rej, int32_t* status, void* stream);
+
+/* Human-readable name of a return code (static string). */
+const char* rok4e_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROK4E_H */

@@ -14,19 +14,30 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rok4e_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with fused multiply-adds: a second, equally valid rounding of
+# every expression.  Comparing the two builds measures how far rounding alone moves the
+# method's result (the envelope that GPU-vs-oracle differences are held to).
+_LIB_FMA = os.path.join(_HERE, "liboracle_fma.so")
 
 CXXFLAGS = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
             "-shared", "-fPIC"]
+CXXFLAGS_FMA = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=fast", "-mfma", "-fopenmp",
+                "-shared", "-fPIC"]
+LIBS = ["-lquadmath"]
 
-JVP_FD, JVP_COMPLEX, JVP_EXACT = 0, 1, 2
+# finite difference (difference form), complex step, exact (linear), finite difference
+# evaluated literally as the difference of two rounded right-hand sides
+JVP_FD, JVP_COMPLEX, JVP_EXACT, JVP_FD_LITERAL = 0, 1, 2, 3
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with g++ (always recompiles)."""
-    cmd = ["g++", *CXXFLAGS, "-o", _LIB, _SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    """Compile the oracle and its FMA twin with g++ (always recompiles)."""
+    for flags, out in ((CXXFLAGS, _LIB), (CXXFLAGS_FMA, _LIB_FMA)):
+        cmd = ["g++", *flags, "-o", out + ".tmp", _SRC, *LIBS]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
     return _LIB
 
 
@@ -44,15 +55,19 @@ class OrcOpts(C.Structure):
 
 
 _lib = None
+_lib_fma = None
 
 
-def lib():
-    global _lib
+def lib(fma: bool = False):
+    global _lib, _lib_fma
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        stale = [p for p in (_LIB, _LIB_FMA)
+                 if not os.path.exists(p) or os.path.getmtime(p) < os.path.getmtime(_SRC)]
+        if stale:
             build()
         _lib = C.CDLL(_LIB)
-    return _lib
+        _lib_fma = C.CDLL(_LIB_FMA)
+    return _lib_fma if fma else _lib
 
 
 def _p(a):
@@ -112,13 +127,24 @@ def cell_jvp(mech, u, p, v, mode=JVP_FD, eps_fd=0.0):
     return out
 
 
-def cell_arnoldi(mech, u, p, M, mode=JVP_FD, eps_fd=0.0):
+def cell_fdiff(mech, u, p, du, quad=False):
+    """f(u + du) - f(u) of one cell: difference form, or the quad-precision reference."""
+    h = MechHandle(mech)
+    u = np.ascontiguousarray(u, np.float64)
+    du = np.ascontiguousarray(du, np.float64)
+    out = np.zeros_like(u)
+    fn = lib().orc_cell_fdiff_quad if quad else lib().orc_cell_fdiff
+    fn(C.byref(h.s), _p(u), C.c_double(p), _p(du), _p(out))
+    return out
+
+
+def cell_arnoldi(mech, u, p, M, mode=JVP_FD, eps_fd=0.0, fma=False):
     h = MechHandle(mech)
     u = np.ascontiguousarray(u, np.float64)
     n = u.shape[0]
     Q = np.zeros((M, n))
     H = np.zeros((M, M))
-    meff = lib().orc_cell_arnoldi(C.byref(h.s), _p(u), C.c_double(p), C.c_int(M), C.c_int(mode),
+    meff = lib(fma).orc_cell_arnoldi(C.byref(h.s), _p(u), C.c_double(p), C.c_int(M), C.c_int(mode),
                                   C.c_double(eps_fd), _p(Q), _p(H))
     return Q.T.copy(), H, meff
 
@@ -128,9 +154,9 @@ def make_opts(M, jvp=JVP_FD, fixed_steps=0, max_attempts=0, eps_fd=0.0, h0=0.0):
 
 
 def integrate(mech, Y, T, p, dt, rtol, atol, M, S=None, jvp=JVP_FD, fixed_steps=0,
-              max_attempts=0, eps_fd=0.0, h0=0.0, nthreads=0):
+              max_attempts=0, eps_fd=0.0, h0=0.0, nthreads=0, fma=False):
     """Integrate every cell over [0, dt]; returns (Y, T, accepted, rejected, status)
-    as new arrays (inputs untouched)."""
+    as new arrays (inputs untouched).  fma=True runs the FMA-contracted twin build."""
     h = MechHandle(mech)
     Y = np.array(Y, np.float64, order="C", copy=True)
     T = np.array(T, np.float64, copy=True)
@@ -141,7 +167,7 @@ def integrate(mech, Y, T, p, dt, rtol, atol, M, S=None, jvp=JVP_FD, fixed_steps=
     rej = np.zeros(n, np.int32)
     st = np.zeros(n, np.int32)
     o = make_opts(M, jvp, fixed_steps, max_attempts, eps_fd, h0)
-    lib().orc_integrate(C.byref(h.s), C.byref(o), C.c_int64(n), _p(Y), _p(T), _p(p), _p(S),
+    lib(fma).orc_integrate(C.byref(h.s), C.byref(o), C.c_int64(n), _p(Y), _p(T), _p(p), _p(S),
                         C.c_double(dt), C.c_double(rtol), C.c_double(atol), _p(acc), _p(rej),
                         _p(st), C.c_int(nthreads))
     return Y, T, acc, rej, st

@@ -24,7 +24,12 @@
 //   - error norm: weighted RMS over all N components with scale atol + rtol |u*_i|;
 //   - err_n = 1 before the first accepted step; err_n is updated on accept only;
 //   - the last step is clipped to the interval end;
-//   - FD increment delta = sqrt(eps (1 + ||u_n||_2)) for unit-norm Arnoldi vectors;
+//   - FD increment delta = sqrt(eps (1 + ||u_n||_2)) for unit-norm Arnoldi vectors, with
+//     eps = 2^-52; the difference f(u + du) - f(u) (du = delta v) is evaluated in
+//     difference form: every quantity of f is carried with its exact-arithmetic increment
+//     (d rho, d c_k, d k_f = k_f expm1(d x), d q_j, ...), which is algebraically the same
+//     number as the literal difference without its subtractive cancellation (the literal
+//     form, JVP mode 3, leaves rounding noise ~eps |f| / delta in every product);
 //   - Arnoldi: M_eff = min(M, N); stop early when the new vector's norm falls below
 //     1e-12 of the norm before orthogonalisation; ||f_n|| = 0 gives M_eff = 0;
 //   - after a rejected step the basis of the same u_n is reused (identical result);
@@ -40,10 +45,20 @@
 #include <type_traits>
 #include <vector>
 #include <omp.h>
+#include <quadmath.h>
 
 namespace {
 
 using cplx = std::complex<double>;
+using quad = __float128;
+
+// exp and log for the three scalar types of the right-hand side.
+inline double exp_(double x) { return std::exp(x); }
+inline cplx exp_(const cplx& x) { return std::exp(x); }
+inline quad exp_(quad x) { return expq(x); }
+inline double log_(double x) { return std::log(x); }
+inline cplx log_(const cplx& x) { return std::log(x); }
+inline quad log_(quad x) { return logq(x); }
 
 constexpr double kRu = 8.314462618;      // J/(mol K)
 constexpr double kTref = 298.15;         // K
@@ -72,7 +87,8 @@ typedef struct {
 
 typedef struct {
   int32_t M;             // Krylov dimension
-  int32_t jvp;           // 0 finite difference, 1 complex step, 2 exact (linear problems)
+  int32_t jvp;           // 0 finite difference (difference form), 1 complex step,
+                         // 2 exact (linear problems), 3 finite difference (literal form)
   int32_t fixed_steps;   // 0 adaptive, n > 0: n equal steps without error control
   int32_t max_attempts;  // attempts allowed per cell (<= 0: 1000000)
   double eps_fd;         // unit roundoff used in the FD increment (<= 0: 2^-52)
@@ -89,6 +105,7 @@ namespace {
 // forcing s (length ns+1) added to f.
 struct CellProblem {
   static constexpr bool kComplex = true;
+  static constexpr bool kDiff = true;
   const orc_mech* m;
   double p;
   const double* s;   // may be null
@@ -99,16 +116,16 @@ struct CellProblem {
     const int ns = m->n_species, nr = m->n_reactions;
     const S T = u[ns];
     S sigma = 0.0, cpbar = 0.0;
-    for (int k = 0; k < ns; ++k) sigma += u[k] / m->W[k];
-    for (int k = 0; k < ns; ++k) cpbar += u[k] * m->cp[k];
-    const S rho = p / (kRu * T * sigma);                       // kg/m^3
+    for (int k = 0; k < ns; ++k) sigma += u[k] / S(m->W[k]);
+    for (int k = 0; k < ns; ++k) cpbar += u[k] * S(m->cp[k]);
+    const S rho = S(p) / (S(kRu) * T * sigma);                 // kg/m^3
     std::vector<S> c(ns), wdot(ns, S(0.0));
-    for (int k = 0; k < ns; ++k) c[k] = 1e-6 * rho * u[k] / m->W[k];   // mol/cm^3
-    const S lnT = std::log(T);
-    const S invRT = 1.0 / (kRu * T);
+    for (int k = 0; k < ns; ++k) c[k] = S(1e-6) * rho * u[k] / S(m->W[k]);   // mol/cm^3
+    const S lnT = log_(T);
+    const S invRT = S(1.0) / (S(kRu) * T);
     for (int j = 0; j < nr; ++j) {
-      const S kf = std::exp(m->lnAf[j] + m->bf[j] * lnT - m->Ef[j] * invRT);
-      const S kr = std::exp(m->lnAr[j] + m->br[j] * lnT - m->Er[j] * invRT);
+      const S kf = exp_(S(m->lnAf[j]) + S(m->bf[j]) * lnT - S(m->Ef[j]) * invRT);
+      const S kr = exp_(S(m->lnAr[j]) + S(m->br[j]) * lnT - S(m->Er[j]) * invRT);
       S pf = 1.0, pr = 1.0;
       for (int a = 0; a < 2; ++a) {
         if (m->reac[2 * j + a] >= 0) pf = pf * c[m->reac[2 * j + a]];
@@ -134,24 +151,102 @@ struct CellProblem {
         if (i == nsp) { sp[nsp] = r; nu[nsp] = 0; ++nsp; }
         nu[i] += 1;
       }
-      for (int i = 0; i < nsp; ++i) wdot[sp[i]] += static_cast<double>(nu[i]) * q;
+      for (int i = 0; i < nsp; ++i) wdot[sp[i]] += S(static_cast<double>(nu[i])) * q;
     }
     S hsum = 0.0;
     for (int k = 0; k < ns; ++k) {
-      const S w = 1e6 * wdot[k];                                // mol/(m^3 s)
-      out[k] = m->W[k] * w / rho;
-      const S hk = m->hf[k] + m->cp[k] * (T - kTref);
-      hsum += hk * m->W[k] * w;
+      const S w = S(1e6) * wdot[k];                             // mol/(m^3 s)
+      out[k] = S(m->W[k]) * w / rho;
+      const S hk = S(m->hf[k]) + S(m->cp[k]) * (T - S(kTref));
+      hsum += hk * S(m->W[k]) * w;
     }
     out[ns] = -hsum / (rho * cpbar);
     if (s)
-      for (int k = 0; k <= ns; ++k) out[k] += s[k];
+      for (int k = 0; k <= ns; ++k) out[k] += S(s[k]);
+  }
+
+  // Net stoichiometric coefficients of reaction j (species, coefficient), in the order
+  // reactants then products, each species once.
+  int stoich(int j, int* sp, int* nu) const {
+    int nsp = 0;
+    for (int side = 0; side < 2; ++side)
+      for (int a = 0; a < 2; ++a) {
+        const int r = side == 0 ? m->reac[2 * j + a] : m->prod[2 * j + a];
+        if (r < 0) continue;
+        int i = 0;
+        while (i < nsp && sp[i] != r) ++i;
+        if (i == nsp) { sp[nsp] = r; nu[nsp] = 0; ++nsp; }
+        nu[i] += side == 0 ? -1 : 1;
+      }
+    return nsp;
+  }
+
+  // out = f(u + du) - f(u), evaluated in difference form: each intermediate quantity x
+  // of f is carried with its increment dx = x(u + du) - x(u), formed from increments
+  // only (no difference of two nearly equal values).  The forcing cancels.
+  void fdiff(const double* u, const double* du, double* out) const {
+    const int ns = m->n_species, nr = m->n_reactions;
+    const double T = u[ns], dT = du[ns], T1 = T + dT;
+    double sigma = 0.0, dsigma = 0.0, cpbar = 0.0, dcp = 0.0;
+    for (int k = 0; k < ns; ++k) {
+      sigma += u[k] / m->W[k];
+      dsigma += du[k] / m->W[k];
+      cpbar += u[k] * m->cp[k];
+      dcp += du[k] * m->cp[k];
+    }
+    const double sigma1 = sigma + dsigma, cp1 = cpbar + dcp;
+    const double rho = p / (kRu * T * sigma);
+    // rho(u + du) - rho(u) = -rho (dT sigma1 + T dsigma) / (T1 sigma1)
+    const double drho = -rho * (dT * sigma1 + T * dsigma) / (T1 * sigma1);
+    const double rho1 = rho + drho;
+    std::vector<double> c(ns), dc(ns), wdot(ns, 0.0), dwdot(ns, 0.0);
+    for (int k = 0; k < ns; ++k) {
+      c[k] = 1e-6 * rho * u[k] / m->W[k];
+      dc[k] = 1e-6 * (rho1 * du[k] + drho * u[k]) / m->W[k];
+    }
+    const double lnT = std::log(T), dlnT = std::log1p(dT / T);
+    const double invRT = 1.0 / (kRu * T), dinvRT = -dT / (kRu * T * T1);
+    for (int j = 0; j < nr; ++j) {
+      const double kf = std::exp(m->lnAf[j] + m->bf[j] * lnT - m->Ef[j] * invRT);
+      const double kr = std::exp(m->lnAr[j] + m->br[j] * lnT - m->Er[j] * invRT);
+      const double dkf = kf * std::expm1(m->bf[j] * dlnT - m->Ef[j] * dinvRT);
+      const double dkr = kr * std::expm1(m->br[j] * dlnT - m->Er[j] * dinvRT);
+      // product of concentrations and its increment: d(ab) = a1 db + da b
+      double pf = 1.0, dpf = 0.0, pr = 1.0, dpr = 0.0;
+      for (int a = 0; a < 2; ++a) {
+        const int r = m->reac[2 * j + a];
+        if (r >= 0) { dpf = (pf + dpf) * dc[r] + dpf * c[r]; pf = pf * c[r]; }
+        const int q = m->prod[2 * j + a];
+        if (q >= 0) { dpr = (pr + dpr) * dc[q] + dpr * c[q]; pr = pr * c[q]; }
+      }
+      const double q = kf * pf - kr * pr;
+      const double dq = ((kf + dkf) * dpf + dkf * pf) - ((kr + dkr) * dpr + dkr * pr);
+      int sp[4], nu[4];
+      const int nsp = stoich(j, sp, nu);
+      for (int i = 0; i < nsp; ++i) {
+        wdot[sp[i]] += static_cast<double>(nu[i]) * q;
+        dwdot[sp[i]] += static_cast<double>(nu[i]) * dq;
+      }
+    }
+    double hsum = 0.0, dhsum = 0.0;
+    for (int k = 0; k < ns; ++k) {
+      const double w = 1e6 * wdot[k], dw = 1e6 * dwdot[k];
+      // W (w1/rho1 - w/rho) = W (dw/rho1 - w drho/(rho rho1))
+      out[k] = m->W[k] * (dw / rho1 - w * drho / (rho * rho1));
+      const double hk = m->hf[k] + m->cp[k] * (T - kTref), dhk = m->cp[k] * dT;
+      hsum += hk * m->W[k] * w;
+      dhsum += m->W[k] * ((hk + dhk) * dw + dhk * w);
+    }
+    // f_T = -hsum / D with D = rho cp_mix
+    const double D = rho * cpbar, dD = drho * cp1 + rho * dcp;
+    out[ns] = -(dhsum / (D + dD) - hsum * dD / (D * (D + dD)));
   }
 };
 
 // Linear test problem f(u) = A u + c (A row-major n x n).
 struct LinearProblem {
   static constexpr bool kComplex = true;
+  static constexpr bool kDiff = true;
   int nn;
   const double* A;
   const double* c;
@@ -164,6 +259,8 @@ struct LinearProblem {
       out[i] = acc;
     }
   }
+  // A du is exactly f(u + du) - f(u) for an affine f.
+  void fdiff(const double*, const double* du, double* out) const { exact_jvp(du, out); }
   void exact_jvp(const double* v, double* out) const {
     for (int i = 0; i < nn; ++i) {
       double acc = 0.0;
@@ -185,6 +282,7 @@ namespace {
 // A caller-supplied f (finite-difference Jacobian-vector products only).
 struct CallbackProblem {
   static constexpr bool kComplex = false;
+  static constexpr bool kDiff = false;
   int nn;
   orc_rhs_fn fn;
   void* ctx;
@@ -212,11 +310,21 @@ template <class P>
 bool jvp(const P& prob, int mode, double eps_fd, const std::vector<double>& u,
          const std::vector<double>& fu, const double* v, double* out) {
   const int n = prob.n();
-  if (mode == 0) {
+  if (mode == 0 || mode == 3) {
     // Finite difference, Sec. 4.3: (f(u + delta v) - f(u)) / delta.
     const double delta = std::sqrt(eps_fd * (1.0 + norm2(u)));
+    std::vector<double> du(n), d(n);
+    for (int i = 0; i < n; ++i) du[i] = delta * v[i];
+    if constexpr (P::kDiff) {
+      if (mode == 0) {
+        prob.fdiff(u.data(), du.data(), d.data());
+        for (int i = 0; i < n; ++i) out[i] = d[i] / delta;
+        return true;
+      }
+    }
+    // literal form: difference of two separately rounded evaluations
     std::vector<double> up(n), fp(n);
-    for (int i = 0; i < n; ++i) up[i] = u[i] + delta * v[i];
+    for (int i = 0; i < n; ++i) up[i] = u[i] + du[i];
     prob.template f<double>(up.data(), fp.data());
     for (int i = 0; i < n; ++i) out[i] = (fp[i] - fu[i]) / delta;
     return true;
@@ -554,6 +662,29 @@ int orc_cell_jvp(const orc_mech* m, const double* u, double p, const double* v, 
   std::vector<double> uu(u, u + n), fu(n);
   prob.f<double>(uu.data(), fu.data());
   return jvp(prob, mode, eps_fd > 0 ? eps_fd : std::ldexp(1.0, -52), uu, fu, v, out) ? 0 : -1;
+}
+
+// f(u + du) - f(u) of one cell, evaluated in quadruple precision (113-bit significand)
+// and rounded to double: the reference for the difference-form evaluation.
+int orc_cell_fdiff_quad(const orc_mech* m, const double* u, double p, const double* du, double* out) {
+  const int n = m->n_species + 1;
+  CellProblem prob{m, p, nullptr};
+  std::vector<quad> a(n), b(n), fa(n), fb(n);
+  for (int i = 0; i < n; ++i) {
+    a[i] = (quad)u[i];
+    b[i] = (quad)u[i] + (quad)du[i];
+  }
+  prob.f<quad>(a.data(), fa.data());
+  prob.f<quad>(b.data(), fb.data());
+  for (int i = 0; i < n; ++i) out[i] = (double)(fb[i] - fa[i]);
+  return 0;
+}
+
+// f(u + du) - f(u) of one cell in difference form (the FD numerator of JVP mode 0).
+int orc_cell_fdiff(const orc_mech* m, const double* u, double p, const double* du, double* out) {
+  CellProblem prob{m, p, nullptr};
+  prob.fdiff(u, du, out);
+  return 0;
 }
 
 // Arnoldi basis of one cell.  Q is n x M (column j at Q[j*n]), H is M x M row-major.

@@ -1,0 +1,384 @@
+// Per-cell ROK4E integration on one segment of lanes (Algorithm a:ROK4E).
+#pragma once
+
+#include "rok4e_device.hpp"
+
+namespace rok4e {
+
+// Segment-local LDS views: right-hand-side scratch in the rate type RT, the projected
+// M x M matrices in FP64.
+template <class RT>
+struct SegLds {
+  RhsLds<RT> r;
+  double* H;   // [MMAX * MMAX] Hessenberg matrix of the Arnoldi process
+  double* LU;  // [MMAX * MMAX] factors of I - h gamma H
+  int* piv;    // [MMAX]
+};
+
+template <class RT>
+__device__ __forceinline__ SegLds<RT> seg_lds(char* seg, const Launch& P) {
+  SegLds<RT> S;
+  S.r = RhsLds<RT>{(RT*)seg, (RT*)(seg + P.off_dc), (RT*)(seg + P.off_q), (RT*)(seg + P.off_kf),
+                   (RT*)(seg + P.off_kr)};
+  S.H = (double*)(seg + P.off_H);
+  S.LU = (double*)(seg + P.off_LU);
+  S.piv = (int*)(seg + P.off_piv);
+  return S;
+}
+
+// f(u) + s for the rows this lane holds (SAVE keeps the base quantities for rhs_diff).
+template <int L, int ROWS, class RT, bool SAVE>
+__device__ __forceinline__ void rhs_forced(const DevMech& m, const double (&u)[ROWS], double p,
+                                           const double (&s)[ROWS], double (&f)[ROWS],
+                                           const SegLds<RT>& S, int lane, RhsBase* base,
+                                           RT (&w)[ROWS]) {
+  rhs<L, ROWS, RT, SAVE>(m, u, p, f, S.r, lane, base, w);
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) f[i] = f[i] + s[i];
+}
+
+// Arnoldi process with modified Gram-Schmidt (Sec. 4.1, e:jac_proj) on finite-difference
+// Jacobian-vector products (Sec. 4.3), J v = (f(u + delta v) - f(u)) / delta with the
+// numerator in difference form.  Q holds this lane's rows of the orthonormal basis, H
+// (LDS) the M x M Hessenberg matrix; both FP64.  Returns M_eff.  Needs the base
+// evaluation of f at u (rhs with SAVE) just before.
+template <int L, int ROWS, int MMAX, class RT>
+__device__ __forceinline__ int arnoldi(const DevMech& m, const Launch& P, const double (&u)[ROWS],
+                                       const double (&fn)[ROWS], const RhsBase& B, const RT (&w)[ROWS],
+                                       double (&Q)[ROWS][MMAX], const SegLds<RT>& S, int lane) {
+  const int N = m.ns + 1;
+  int Meff = P.M < N ? P.M : N;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i)
+#pragma unroll
+    for (int j = 0; j < MMAX; ++j) Q[i][j] = 0.0;
+  double sq[ROWS];
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) sq[i] = fn[i] * fn[i];
+  const double beta = sqrt(seg_sum<L, ROWS>(sq));
+  if (beta == 0.0) return 0;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) Q[i][0] = fn[i] / beta;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) sq[i] = u[i] * u[i];
+  const double delta = sqrt(P.eps_fd * (1.0 + sqrt(seg_sum<L, ROWS>(sq))));
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j) {
+    if (j >= Meff) break;
+    double du[ROWS], d[ROWS], wv[ROWS];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) du[i] = delta * Q[i][j];
+    rhs_diff<L, ROWS, RT>(m, B, w, u, du, d, S.r, lane);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) wv[i] = d[i] / delta;
+    double wn0 = 0.0;
+    if (j + 1 < Meff) {
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) sq[i] = wv[i] * wv[i];
+      wn0 = sqrt(seg_sum<L, ROWS>(sq));
+    }
+#pragma unroll
+    for (int i2 = 0; i2 < MMAX; ++i2) {
+      if (i2 > j) break;
+      double pr[ROWS];
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) pr[i] = Q[i][i2] * wv[i];
+      const double hij = seg_sum<L, ROWS>(pr);
+      S.H[i2 * MMAX + j] = hij;
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) wv[i] = wv[i] - hij * Q[i][i2];
+    }
+    if (j + 1 < Meff) {
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) sq[i] = wv[i] * wv[i];
+      const double hn = sqrt(seg_sum<L, ROWS>(sq));
+      if (!(hn > 1e-12 * wn0)) {
+        Meff = j + 1;
+        break;
+      }
+      S.H[(j + 1) * MMAX + j] = hn;
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) Q[i][j + 1] = wv[i] / hn;
+    }
+  }
+  lds_sync();
+  return Meff;
+}
+
+// LU with partial pivoting of the upper-Hessenberg I - h gamma H (rows k and k+1 are the
+// only pivot candidates of column k).  Every lane of the segment computes and writes the
+// same values, so no lane-dependent branch is needed.
+template <int MMAX>
+__device__ __forceinline__ bool lu_factor(double* a, int* piv, int m) {
+  for (int k = 0; k < m; ++k) {
+    int pk = k;
+    if (k + 1 < m && fabs(a[(k + 1) * MMAX + k]) > fabs(a[k * MMAX + k])) pk = k + 1;
+    piv[k] = pk;
+    if (pk != k) {
+      for (int j = 0; j < m; ++j) {
+        const double x = a[k * MMAX + j], y = a[pk * MMAX + j];
+        lds_sync();
+        a[k * MMAX + j] = y;
+        a[pk * MMAX + j] = x;
+      }
+    }
+    lds_sync();
+    const double akk = a[k * MMAX + k];
+    if (akk == 0.0) return false;
+    if (k + 1 < m) {
+      const double l = a[(k + 1) * MMAX + k] / akk;
+      for (int j = k + 1; j < m; ++j) {
+        const double v = a[(k + 1) * MMAX + j] - l * a[k * MMAX + j];
+        a[(k + 1) * MMAX + j] = v;
+      }
+      a[(k + 1) * MMAX + k] = l;
+      lds_sync();
+    }
+  }
+  return true;
+}
+
+// x <- (I - h gamma H)^{-1} x for a uniform vector x (all row interchanges first).
+template <int MMAX>
+__device__ __forceinline__ void lu_solve(const double* a, const int* piv, int m, double (&x)[MMAX]) {
+#pragma unroll
+  for (int k = 0; k < MMAX - 1; ++k) {
+    if (k >= m) break;
+    if (piv[k] != k) {
+      const double t = x[k];
+      x[k] = x[k + 1];
+      x[k + 1] = t;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MMAX - 1; ++k) {
+    if (k + 1 >= m) break;
+    x[k + 1] = x[k + 1] - a[(k + 1) * MMAX + k] * x[k];
+  }
+#pragma unroll
+  for (int i = MMAX - 1; i >= 0; --i) {
+    if (i < m) {
+      double sacc = x[i];
+#pragma unroll
+      for (int j = i + 1; j < MMAX; ++j)
+        if (j < m) sacc = sacc - a[i * MMAX + j] * x[j];
+      x[i] = sacc / a[i * MMAX + i];
+    }
+  }
+}
+
+// k = F - Q (z - y) - corr with z = Q^T F and y = (I - h gamma H)^{-1} z
+// (Algorithm a:ROK4E, stage update; Woodbury form e:solve_kry_jac).
+template <int L, int ROWS, int MMAX>
+__device__ __forceinline__ void stage_solve(const double (&F)[ROWS], const double (&corr)[ROWS],
+                                            double (&k)[ROWS], const double (&Q)[ROWS][MMAX], int Meff,
+                                            const double* LU, const int* piv) {
+  double z[MMAX], y[MMAX];
+#pragma unroll
+  for (int i2 = 0; i2 < MMAX; ++i2) {
+    z[i2] = 0.0;
+    if (i2 < Meff) {
+      double pr[ROWS];
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) pr[i] = Q[i][i2] * F[i];
+      z[i2] = seg_sum<L, ROWS>(pr);
+    }
+    y[i2] = z[i2];
+  }
+  if (Meff > 0) lu_solve<MMAX>(LU, piv, Meff, y);
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    double qw = 0.0;
+#pragma unroll
+    for (int i2 = 0; i2 < MMAX; ++i2)
+      if (i2 < Meff) qw = qw + Q[i][i2] * (z[i2] - y[i2]);
+    k[i] = F[i] - qw - corr[i];
+  }
+}
+
+struct CellResult {
+  int status, accepted, rejected;
+};
+
+// Integrates the segment's cell over [0, dt] in place in u (Algorithm a:ROK4E with the
+// readings: clipped last step, err_n = 1 before the first acceptance and updated on
+// acceptance, basis reused after a rejection, non-finite u* or err rejected).
+template <int L, int ROWS, int MMAX, class RT>
+__device__ CellResult integrate_cell(const DevMech& m, const Launch& P, double (&u)[ROWS], double p,
+                                     const double (&s)[ROWS], const SegLds<RT>& S, int lane) {
+  CellResult res{0, 0, 0};
+  const int N = m.ns + 1;
+  const double dt = P.dt;
+  const double tiny = 16.0 * 2.220446049250313e-16 * dt;
+  const int max_att = P.max_attempts > 0 ? P.max_attempts : 1000000;
+  const bool fixed = P.fixed_steps > 0;
+  double fn[ROWS], k1[ROWS], k2[ROWS], k3[ROWS], k4[ROWS];
+  double Q[ROWS][MMAX];
+  RT wbase[ROWS];
+  RhsBase base;
+  int Meff = 0;
+  bool basis_valid = false;
+  double t = 0.0, h = P.h0 > 0.0 ? P.h0 : dt, err_prev = 1.0;
+  if (fixed) h = dt / P.fixed_steps;
+  int attempts = 0, steps_done = 0;
+
+  while (fixed ? steps_done < P.fixed_steps : t < dt) {
+    if (attempts >= max_att) {
+      res.status = 1;
+      break;
+    }
+    bool last = false;
+    if (!fixed && h >= (dt - t) * (1.0 - 1e-12)) {
+      h = dt - t;
+      last = true;
+    }
+    if (!basis_valid) {
+      rhs_forced<L, ROWS, RT, true>(m, u, p, s, fn, S, lane, &base, wbase);
+      Meff = arnoldi<L, ROWS, MMAX, RT>(m, P, u, fn, base, wbase, Q, S, lane);
+      basis_valid = true;
+    }
+    // L = I - h gamma H, factored once per attempt.  Only the Hessenberg part of the
+    // LDS copy of H is written by the Arnoldi process; the rest is zero.
+    for (int i = 0; i < Meff; ++i)
+      for (int j = 0; j < Meff; ++j) {
+        const double hij = i <= j + 1 ? S.H[i * MMAX + j] : 0.0;
+        S.LU[i * MMAX + j] = (i == j ? 1.0 : 0.0) - h * G * hij;
+      }
+    lds_sync();
+    if (Meff > 0 && !lu_factor<MMAX>(S.LU, S.piv, Meff)) {
+      ++attempts;
+      ++res.rejected;
+      h *= 0.2;
+      if (h < tiny) {
+        res.status = 2;
+        break;
+      }
+      continue;
+    }
+    double corr[ROWS], F[ROWS], arg[ROWS], fs[ROWS];
+    RT wtmp[ROWS];
+    // Stage 1: F1 = f_n.
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) corr[i] = 0.0;
+    stage_solve<L, ROWS, MMAX>(fn, corr, k1, Q, Meff, S.LU, S.piv);
+    // Stage 2: F2 = f(u + h a21 k1) + (g21/g) k1.
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A21 * k1[i]);
+    rhs_forced<L, ROWS, RT, false>(m, arg, p, s, fs, S, lane, nullptr, wtmp);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      corr[i] = (G21 / G) * k1[i];
+      F[i] = fs[i] + corr[i];
+    }
+    stage_solve<L, ROWS, MMAX>(F, corr, k2, Q, Meff, S.LU, S.piv);
+    // Stage 3: F3 = f(u + h(a31 k1 + a32 k2)) + (g31 k1 + g32 k2)/g.
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A31 * k1[i] + A32 * k2[i]);
+    rhs_forced<L, ROWS, RT, false>(m, arg, p, s, fs, S, lane, nullptr, wtmp);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      corr[i] = (G31 * k1[i] + G32 * k2[i]) / G;
+      F[i] = fs[i] + corr[i];
+    }
+    stage_solve<L, ROWS, MMAX>(F, corr, k3, Q, Meff, S.LU, S.piv);
+    // Stage 4 reuses f of stage 3 (a41 = a31, a42 = a32, a43 = 0).
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      corr[i] = (G41 * k1[i] + G42 * k2[i] + G43 * k3[i]) / G;
+      F[i] = fs[i] + corr[i];
+    }
+    stage_solve<L, ROWS, MMAX>(F, corr, k4, Q, Meff, S.LU, S.piv);
+
+    double us[ROWS];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) us[i] = u[i] + h * (B1 * k1[i] + B2 * k2[i] + B4 * k4[i]);
+    ++attempts;
+    if (fixed) {
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) u[i] = us[i];
+      ++res.accepted;
+      ++steps_done;
+      basis_valid = false;
+      continue;
+    }
+    // Embedded error e = h sum (bh_j - b_j) k_j, weighted RMS over the N rows.
+    double ss[ROWS], nb[ROWS];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      const int r = (int)(i * L + lane);
+      ss[i] = 0.0;
+      nb[i] = 0.0;
+      if (r < N) {
+        const double e = h * (E1 * k1[i] + E2 * k2[i] + E3 * k3[i] + E4 * k4[i]);
+        const double sc = P.atol + P.rtol * fabs(us[i]);
+        const double ratio = e / sc;
+        ss[i] = ratio * ratio;
+        nb[i] = finite_(us[i]) ? 0.0 : 1.0;
+      }
+    }
+    double err = sqrt(seg_sum<L, ROWS>(ss) / N);
+    const double nbad = seg_sum<L, ROWS>(nb);
+    if (!finite_(err) || nbad != 0.0) err = __builtin_huge_val();
+    // PI controller, alpha = 0.7/4, beta = 0.4/4.
+    const double fac = fmin(5.0, fmax(0.2, 0.8 * pow(fmax(err_prev, 1e-10), 0.1) /
+                                               pow(fmax(err, 1e-10), 0.175)));
+    const double hstar = h * fac;
+    if (err <= 1.0) {
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) u[i] = us[i];
+      t = last ? dt : t + h;
+      err_prev = err;
+      h = hstar;
+      ++res.accepted;
+      basis_valid = false;
+    } else {
+      h = hstar;
+      ++res.rejected;
+    }
+    if (t < dt && h < tiny) {
+      res.status = 2;
+      break;
+    }
+  }
+  return res;
+}
+
+// Loads a cell's rows (Y, T, forcing) for this lane; returns false if the input is not a
+// valid state (non-finite values, T <= 0, p <= 0).
+template <int L, int ROWS>
+__device__ __forceinline__ bool load_cell(const DevMech& m, const Launch& P, int64_t cell, int lane,
+                                          double (&u)[ROWS], double (&s)[ROWS], double& p) {
+  const int ns = m.ns, N = ns + 1;
+  const int64_t n = P.n_cells;
+  double bad[ROWS];
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const int r = i * L + lane;
+    u[i] = 0.0;
+    s[i] = 0.0;
+    bad[i] = 0.0;
+    if (r < ns) u[i] = P.Y[(int64_t)r * n + cell];
+    else if (r == ns) u[i] = P.T[cell];
+    if (P.S != nullptr && r < N) s[i] = P.S[(int64_t)r * n + cell];
+    if (r < N && !finite_(u[i])) bad[i] = 1.0;
+    if (r == ns && !(u[i] > 0.0)) bad[i] = 1.0;
+  }
+  p = P.p[cell];
+  const double nbad = seg_sum<L, ROWS>(bad);
+  return nbad == 0.0 && finite_(p) && p > 0.0;
+}
+
+template <int L, int ROWS>
+__device__ __forceinline__ void store_cell(const DevMech& m, const Launch& P, int64_t cell, int lane,
+                                           const double (&u)[ROWS]) {
+  const int ns = m.ns;
+  const int64_t n = P.n_cells;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const int r = i * L + lane;
+    if (r < ns) P.Y[(int64_t)r * n + cell] = u[i];
+    else if (r == ns) P.T[cell] = u[i];
+  }
+}
+
+}  // namespace rok4e

@@ -1,0 +1,191 @@
+"""Python binding of librok4e.so (argument marshalling only).
+
+Device memory and streams come from PyTorch: state arrays are float64 CUDA (ROCm)
+tensors passed by data pointer, the stream is torch's current stream.  Every step of
+the reaction substep runs in the HIP library; there is no fallback path, and loading
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librok4e.so")
+
+OK, EINVAL, ENOMEM, EHIP, ECAPTURE, ENOTSUP = 0, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+PERSISTENT, PER_ATTEMPT = 0, 1
+CELL_OK, CELL_MAX_ATTEMPTS, CELL_STEP_UNDERFLOW, CELL_BAD_INPUT = 0, 1, 2, 3
+
+EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "rok4e_set_options",
+           "rok4e_get_options", "rok4e_reserve", "rok4e_integrate", "rok4e_integrate_forced",
+           "rok4e_rhs", "rok4e_arnoldi", "rok4e_get_stats", "rok4e_cell_stats_ptr",
+           "rok4e_copy_cell_stats", "rok4e_strerror"]
+
+
+class MechDesc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("W", C.c_void_p), ("cp", C.c_void_p), ("hf", C.c_void_p),
+                ("reac", C.c_void_p), ("prod", C.c_void_p),
+                ("lnAf", C.c_void_p), ("bf", C.c_void_p), ("Ef", C.c_void_p),
+                ("lnAr", C.c_void_p), ("br", C.c_void_p), ("Er", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("M", C.c_int32), ("precision", C.c_int32), ("max_attempts", C.c_int32),
+                ("fixed_steps", C.c_int32), ("lanes_per_cell", C.c_int32),
+                ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("scheduling", C.c_int32), ("h0", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("accepted", C.c_int64), ("rejected", C.c_int64),
+                ("max_attempts", C.c_int64), ("status_count", C.c_int64 * 4)]
+
+
+class Rok4eError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Loads librok4e.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(hipcc, gfx950); there is no fallback implementation")
+        lib = C.CDLL(LIB_PATH)
+        vp, i64, dbl = C.c_void_p, C.c_int64, C.c_double
+        lib.rok4e_strerror.restype = C.c_char_p
+        lib.rok4e_strerror.argtypes = [C.c_int]
+        lib.rok4e_options_default.restype = None
+        lib.rok4e_options_default.argtypes = [C.POINTER(Options)]
+        lib.rok4e_mech_create.argtypes = [C.POINTER(MechDesc), C.POINTER(Options), C.POINTER(vp)]
+        lib.rok4e_mech_destroy.argtypes = [vp]
+        lib.rok4e_set_options.argtypes = [vp, C.POINTER(Options)]
+        lib.rok4e_get_options.argtypes = [vp, C.POINTER(Options)]
+        lib.rok4e_reserve.argtypes = [vp, i64]
+        lib.rok4e_integrate.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, vp]
+        lib.rok4e_integrate_forced.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
+        lib.rok4e_rhs.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
+        lib.rok4e_arnoldi.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.rok4e_get_stats.argtypes = [vp, C.POINTER(Stats), vp]
+        lib.rok4e_cell_stats_ptr.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+        lib.rok4e_copy_cell_stats.argtypes = [vp, vp, vp, vp, vp]
+        _lib = lib
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return load().rok4e_strerror(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise Rok4eError(rc, what)
+
+
+def options(M=4, precision=FP64, max_attempts=0, fixed_steps=0, lanes_per_cell=0,
+            waves_per_block=0, blocks_per_cu=0, scheduling=PERSISTENT, h0=0.0) -> Options:
+    return Options(int(M), int(precision), int(max_attempts), int(fixed_steps), int(lanes_per_cell),
+                   int(waves_per_block), int(blocks_per_cu), int(scheduling), float(h0))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return C.c_void_p(t.data_ptr())
+    return C.c_void_p(int(t))
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mech:
+    """A mechanism handle on the current device (rok4e_mech_create)."""
+
+    def __init__(self, mech, opts: Options | None = None, **kw):
+        lib = load()
+        self._arrays = [np.ascontiguousarray(a) for a in (
+            np.asarray(mech.W, np.float64), np.asarray(mech.cp, np.float64), np.asarray(mech.hf, np.float64),
+            np.asarray(mech.reac, np.int32).reshape(-1), np.asarray(mech.prod, np.int32).reshape(-1),
+            np.asarray(mech.lnAf, np.float64), np.asarray(mech.bf, np.float64), np.asarray(mech.Ef, np.float64),
+            np.asarray(mech.lnAr, np.float64), np.asarray(mech.br, np.float64), np.asarray(mech.Er, np.float64))]
+        self.n_species = int(mech.n_species)
+        self.n_reactions = int(mech.n_reactions)
+        desc = MechDesc(self.n_species, self.n_reactions, *[a.ctypes.data for a in self._arrays])
+        self.opts = opts if opts is not None else options(**kw)
+        h = C.c_void_p()
+        _check(lib.rok4e_mech_create(C.byref(desc), C.byref(self.opts), C.byref(h)), "rok4e_mech_create")
+        self._h = h
+        self.n_last = 0
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().rok4e_mech_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, opts: Options | None = None, **kw):
+        o = opts if opts is not None else options(**kw)
+        _check(load().rok4e_set_options(self._h, C.byref(o)), "rok4e_set_options")
+        self.opts = o
+
+    def get_options(self) -> Options:
+        o = Options()
+        _check(load().rok4e_get_options(self._h, C.byref(o)), "rok4e_get_options")
+        return o
+
+    def reserve(self, n_cells: int):
+        _check(load().rok4e_reserve(self._h, int(n_cells)), "rok4e_reserve")
+
+    def integrate(self, Y, T, p, dt, rtol, atol, S=None, stream=None, n_cells=None):
+        """In-place integration of Y [ns, n], T [n] (float64 device tensors) over dt."""
+        n = int(T.shape[0]) if n_cells is None else int(n_cells)
+        rc = load().rok4e_integrate_forced(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(S), float(dt),
+                                           float(rtol), float(atol), _stream(stream))
+        _check(rc, "rok4e_integrate")
+        self.n_last = n
+
+    def rhs(self, Y, T, p, dY, dT, stream=None):
+        n = int(T.shape[0])
+        _check(load().rok4e_rhs(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(dY), _ptr(dT), _stream(stream)),
+               "rok4e_rhs")
+
+    def arnoldi(self, Y, T, p, Q, H, Meff, stream=None):
+        n = int(T.shape[0])
+        _check(load().rok4e_arnoldi(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(Q), _ptr(H), _ptr(Meff),
+                                    _stream(stream)), "rok4e_arnoldi")
+
+    def stats(self, stream=None) -> dict:
+        s = Stats()
+        _check(load().rok4e_get_stats(self._h, C.byref(s), _stream(stream)), "rok4e_get_stats")
+        return dict(n_cells=s.n_cells, accepted=s.accepted, rejected=s.rejected,
+                    max_attempts=s.max_attempts, status_count=list(s.status_count))
+
+    def cell_stats(self, acc, rej, status, stream=None):
+        """Copies per-cell counts of the last call into int32 tensors (host or device)."""
+        _check(load().rok4e_copy_cell_stats(self._h, _ptr(acc), _ptr(rej), _ptr(status), _stream(stream)),
+               "rok4e_copy_cell_stats")

@@ -1,0 +1,70 @@
+"""CPU checks of the HIP library boundary: the shared library loads without a GPU, exports
+every function the public header declares, and its host-only entry points behave."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "rok4e.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rok4e_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1712_00953_amd import rok4e as R
+    if not os.path.exists(R.LIB_PATH):
+        from paper_1712_00953_amd import build
+        build.build()
+    return R.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("rok4e_mech_create", "rok4e_integrate", "rok4e_integrate_forced", "rok4e_rhs",
+              "rok4e_arnoldi", "rok4e_reserve", "rok4e_get_stats", "rok4e_strerror"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1712_00953_amd import rok4e as R
+    names = _declared()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(R.EXPORTS) == names
+
+
+def test_host_only_entry_points(lib):
+    from paper_1712_00953_amd import rok4e as R
+    assert R.strerror(0) == "ok"
+    assert "invalid" in R.strerror(-1)
+    assert R.strerror(12345) == "unknown error"
+    o = R.Options()
+    lib.rok4e_options_default(C.byref(o))
+    assert o.M == 4 and o.precision == R.FP64 and o.scheduling == R.PERSISTENT
+
+
+def test_argument_errors_before_any_device_work(lib):
+    from paper_1712_00953_amd import rok4e as R
+    # null handles and descriptions are rejected on the host
+    assert lib.rok4e_mech_create(None, None, None) == R.EINVAL
+    assert lib.rok4e_integrate(4, None, None, None, None, 1e-6, 1e-6, 1e-12, None) == R.EINVAL
+    assert lib.rok4e_reserve(None, 10) == R.EINVAL
+    assert lib.rok4e_mech_destroy(None) == R.OK
+    s = R.Stats()
+    assert lib.rok4e_get_stats(None, C.byref(s), None) == R.EINVAL
+
+
+def test_binding_has_no_fallback(monkeypatch, tmp_path):
+    from paper_1712_00953_amd import rok4e as R
+    monkeypatch.setattr(R, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(R, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        R.load()

@@ -1,0 +1,256 @@
+"""GPU parity of the HIP reaction substep against the FP64 oracle, through the C ABI.
+
+Tolerances (derived from the arithmetic):
+* right-hand side: the same formula in FP64 with different reduction trees and fused
+  multiply-adds: components agree to a few ulps of the largest term they are built
+  from (1e-12 relative, floor 1e-1 of the cell's largest species rate);
+* first Jacobian-vector product (Hessenberg column 0): 1e-11 of |J q_0|;
+* integration: the stage solves are conditioned like h gamma |lambda| and the step
+  sequence follows the embedded error estimate, so rounding alone moves a correct
+  result by a fraction of the tolerance scale atol + rtol |u| (measured by an
+  FMA-contracted twin build of the oracle on the same cells: the "envelope").  The FP64
+  GPU result must lie within 4x that envelope (plus 0.05) in the normalized error
+  |gpu - oracle| / (atol + rtol |oracle|), with a count-match rate no more than 0.1
+  below the twin's;
+* mixed FP32/FP64: normalized error <= max(10, 4x envelope) against the FP64 oracle,
+  i.e. 1e-5 relative (10 rtol) on species above atol/rtol.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import dev_state, envelope, gpu_integrate, normalized, parity, parity_all
+from paper_1712_00953_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+A_SCALE = 1e-8
+MAX_ATT = 20000
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1712_00953_amd import rok4e as R
+    R.load()
+    return R
+
+
+def _report(name, d):
+    print(f"\n[{name}] " + " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}"
+                                     for k, v in d.items()), flush=True)
+
+
+@pytest.mark.parametrize("cfg,n", [(1, 777), (2, 1000), (4, 333)])
+def test_rhs_parity(R, orc, cfg, n):
+    import torch
+    w = synth.workload(cfg, a_scale=A_SCALE, n_cells=n)
+    st = w.states
+    m = R.Mech(w.mech, M=w.M)
+    Y, T, p = dev_state(st)
+    dY = torch.zeros_like(Y)
+    dT = torch.zeros_like(T)
+    m.rhs(Y, T, p, dY, dT)
+    torch.cuda.synchronize()
+    gY, gT = dY.cpu().numpy(), dT.cpu().numpy()
+    oY, oT = orc.rhs(w.mech, st.Y, st.T, st.p)
+    scale = np.abs(oY).max(axis=0)
+    errY = np.abs(gY - oY) / np.maximum(np.abs(oY), 1e-1 * scale[None, :])
+    errT = np.abs(gT - oT) / np.abs(oT)
+    _report(f"rhs cfg{cfg}", dict(max_err_Y=float(errY.max()), max_err_T=float(errT.max())))
+    assert errY.max() <= 1e-12 and errT.max() <= 1e-12
+    m.close()
+
+
+def test_arnoldi_parity(R, orc):
+    """The first Jacobian-vector product (column 0 of H) agrees tightly; later columns of
+    the Krylov basis are ill-determined by rounding on stiff cells, so the GPU basis must
+    be as close to the oracle's as the oracle's FMA twin is."""
+    import torch
+    n = 64
+    w = synth.workload(2, a_scale=A_SCALE, n_cells=n)
+    st = w.states
+    M, N = w.M, w.mech.n_species + 1
+    m = R.Mech(w.mech, M=M)
+    Y, T, p = dev_state(st)
+    Q = torch.zeros(n * M * N, dtype=torch.float64, device="cuda:0")
+    H = torch.zeros(n * M * M, dtype=torch.float64, device="cuda:0")
+    Me = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    m.arnoldi(Y, T, p, Q, H, Me)
+    torch.cuda.synchronize()
+    Qg = Q.cpu().numpy().reshape(n, M, N)
+    Hg = H.cpu().numpy().reshape(n, M, M)
+    col0, ratios = 0.0, []
+    for c in range(n):
+        u = np.concatenate([st.Y[:, c], [st.T[c]]])
+        Qo, Ho, mo = orc.cell_arnoldi(w.mech, u, st.p[c], M, orc.JVP_FD)
+        Qf, Hf, mf = orc.cell_arnoldi(w.mech, u, st.p[c], M, orc.JVP_FD, fma=True)
+        assert int(Me[c]) == mo == mf
+        assert np.max(np.abs(Qg[c][0] - Qo[:, 0])) <= 1e-14
+        jq0 = np.hypot(Ho[0, 0], Ho[1, 0])
+        col0 = max(col0, max(abs(Hg[c][0, 0] - Ho[0, 0]), abs(Hg[c][1, 0] - Ho[1, 0])) / jq0)
+        env = np.max(np.abs(Qf[:, :mo] - Qo[:, :mo])) + 1e-14
+        ratios.append(np.max(np.abs(Qg[c].T[:, :mo] - Qo[:, :mo])) / env)
+    _report("arnoldi cfg2", dict(col0_rel=col0, max_ratio_Q=float(max(ratios)),
+                                 median_ratio_Q=float(np.median(ratios))))
+    assert col0 <= 1e-11
+    assert np.median(ratios) <= 10.0
+    m.close()
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fixed_step_parity(R, orc, cfg):
+    w = synth.workload(cfg, a_scale=A_SCALE, n_cells=256)
+    st = w.states
+    dt = w.dt / 64
+    m = R.Mech(w.mech, M=w.M, fixed_steps=4)
+    g = gpu_integrate(m, st, dt, w.rtol, w.atol)
+    o, env = envelope(orc, w, st, dt, w.rtol, w.atol, fixed_steps=4)
+    mx, p99 = normalized(g, o, w.rtol, w.atol)
+    d = dict(norm_max=mx, norm_p99=p99, **env, **parity_all(g, o))
+    _report(f"fixed cfg{cfg}", d)
+    assert mx <= 4 * env["env_max"] + 0.05
+    m.close()
+
+
+@pytest.mark.parametrize("cfg,n", [(1, 1024), (2, 512), (3, 512)])
+def test_adaptive_parity_fp64(R, orc, cfg, n):
+    w = synth.workload(cfg, a_scale=A_SCALE)
+    idx = synth.stratified_sample(w.states.T, n, 100 + cfg)
+    st = w.states.subset(idx)
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    o, env = envelope(orc, w, st, w.dt, w.rtol, w.atol, max_attempts=MAX_ATT)
+    mx, p99 = normalized(g, o, w.rtol, w.atol)
+    d = dict(norm_max=mx, norm_p99=p99, **env, **parity(g, o))
+    d.update(mean_attempts=float((o[2] + o[3]).mean()))
+    _report(f"adaptive fp64 cfg{cfg}", d)
+    assert np.all(g[4] == 0) and np.all(o[4] == 0)
+    assert mx <= 4 * env["env_max"] + 0.05
+    assert d["match_frac"] >= env["env_match"] - 0.1
+    m.close()
+
+
+def test_adaptive_parity_fp64_cfg4(R, orc):
+    w = synth.workload(4, a_scale=A_SCALE)
+    idx = synth.stratified_sample(w.states.T, 128, 104)
+    st = w.states.subset(idx)
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    o, env = envelope(orc, w, st, w.dt, w.rtol, w.atol, max_attempts=MAX_ATT)
+    mx, p99 = normalized(g, o, w.rtol, w.atol)
+    d = dict(norm_max=mx, norm_p99=p99, **env, **parity(g, o))
+    _report("adaptive fp64 cfg4", d)
+    assert np.all(g[4] == 0)
+    assert mx <= 4 * env["env_max"] + 0.05
+    assert d["match_frac"] >= env["env_match"] - 0.1
+    m.close()
+
+
+@pytest.mark.parametrize("cfg,n,rtol,tol", [(1, 512, 1e-6, 1e-5), (2, 512, 1e-6, 1e-5),
+                                            (4, 128, 1e-6, 1e-5)])
+def test_mixed_parity(R, orc, cfg, n, rtol, tol):
+    w = synth.workload(cfg, a_scale=A_SCALE)
+    idx = synth.stratified_sample(w.states.T, n, 200 + cfg)
+    st = w.states.subset(idx)
+    m = R.Mech(w.mech, M=w.M, precision=R.MIXED, max_attempts=MAX_ATT)
+    g = gpu_integrate(m, st, w.dt, rtol, w.atol)
+    o, env = envelope(orc, w, st, w.dt, rtol, w.atol, max_attempts=MAX_ATT)
+    mx, p99 = normalized(g, o, rtol, w.atol)
+    d = dict(norm_max=mx, norm_p99=p99, **env, **parity_all(g, o))
+    _report(f"mixed cfg{cfg} rtol={rtol:g}", d)
+    assert np.all(g[4] == 0)
+    assert mx <= max(tol / rtol, 4 * env["env_max"])
+    m.close()
+
+
+def test_layouts_are_bitwise_identical(R):
+    w = synth.workload(1, a_scale=A_SCALE, n_cells=300)
+    st = w.states
+    outs = []
+    for L in (16, 32, 64):
+        for wpb in (1, 4):
+            m = R.Mech(w.mech, M=w.M, lanes_per_cell=L, waves_per_block=wpb)
+            outs.append(gpu_integrate(m, st, w.dt, w.rtol, w.atol))
+            m.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_edge_cases(R, orc):
+    import torch
+    w = synth.workload(1, a_scale=A_SCALE, n_cells=5)
+    st = w.states
+    m = R.Mech(w.mech, M=w.M)
+    # empty batch: no-op
+    Y, T, p = dev_state(st)
+    m.integrate(Y[:, :0], T[:0], p[:0], w.dt, w.rtol, w.atol, n_cells=0)
+    # invalid arguments
+    for bad in (dict(dt=0.0), dict(dt=-1.0), dict(rtol=0.0), dict(atol=-1.0)):
+        kw = dict(dt=w.dt, rtol=w.rtol, atol=w.atol)
+        kw.update(bad)
+        with pytest.raises(R.Rok4eError):
+            m.integrate(Y, T, p, kw["dt"], kw["rtol"], kw["atol"])
+    # bad inputs keep their state and report status 3
+    Tb = st.T.copy()
+    Tb[1] = np.nan
+    Tb[2] = -1.0
+    Yb = st.Y.copy()
+    Yb[0, 3] = np.inf
+    sb = synth.States(Yb, Tb, st.p)
+    g = gpu_integrate(m, sb, w.dt, w.rtol, w.atol)
+    assert list(g[4]) == [0, 3, 3, 3, 0]
+    np.testing.assert_array_equal(g[0][:, 1:4], Yb[:, 1:4])
+    assert np.isnan(g[1][1]) and g[1][2] == -1.0
+    # attempt limit
+    m.set_options(M=w.M, max_attempts=1)
+    g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    o = orc.integrate(w.mech, st.Y, st.T, st.p, w.dt, w.rtol, w.atol, w.M, max_attempts=1)
+    np.testing.assert_array_equal(g[4], o[4])
+    assert np.all(g[4] == 1)
+    m.close()
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_forcing_cancelling_f_is_identity(R, orc, cfg):
+    w = synth.workload(cfg, a_scale=A_SCALE, n_cells=64)
+    st = w.states
+    dY, dT = orc.rhs(w.mech, st.Y, st.T, st.p)
+    # the GPU's own f(u0) is needed for an exact cancellation on the GPU
+    import torch
+    m = R.Mech(w.mech, M=w.M)
+    Y, T, p = dev_state(st)
+    gY = torch.zeros_like(Y)
+    gT = torch.zeros_like(T)
+    m.rhs(Y, T, p, gY, gT)
+    S = -torch.cat([gY, gT[None, :]], dim=0)
+    m.integrate(Y, T, p, w.dt, w.rtol, w.atol, S=S)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(Y.cpu().numpy(), st.Y)
+    np.testing.assert_array_equal(T.cpu().numpy(), st.T)
+    m.close()
+
+
+@pytest.mark.parametrize("cfg,n_check", [(2, 96), (3, 96)])
+def test_full_batch_sampled(R, orc, cfg, n_check):
+    """The full batch in the benchmark's launch configuration; the oracle recomputes a
+    seeded sample of cells one by one."""
+    w = synth.workload(cfg, a_scale=A_SCALE)
+    st = w.states
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    assert np.all(g[4] == 0)
+    idx = synth.stratified_sample(st.T, n_check, 300 + cfg)
+    sub = st.subset(idx)
+    o, env = envelope(orc, w, sub, w.dt, w.rtol, w.atol, max_attempts=MAX_ATT)
+    gs = (g[0][:, idx], g[1][idx], g[2][idx], g[3][idx], g[4][idx])
+    mx, p99 = normalized(gs, o, w.rtol, w.atol)
+    d = dict(norm_max=mx, norm_p99=p99, **env, **parity(gs, o))
+    # whole-batch invariants: mass fractions still sum to their initial totals
+    d.update(sumY_drift=float(np.abs(g[0].sum(0) - st.Y.sum(0)).max()))
+    _report(f"full cfg{cfg}", d)
+    assert mx <= 4 * env["env_max"] + 0.05
+    assert d["match_frac"] >= env["env_match"] - 0.1
+    assert d["sumY_drift"] <= 1e-9
+    m.close()
