@@ -1,0 +1,202 @@
+"""Benchmark of the batched ROK4E reaction substep on one MI355X.
+
+One step = one reaction substep (Algorithm a:ROK4E over dt) for every cell of the batch,
+with the cell states already resident in HBM.  Workload: the 53-species / 325-reaction
+synthetic mechanism on a 256 x 256 flame slice (65,536 cells), M = 8, dt = 1e-5 s,
+rtol = 1e-6, atol = 1e-12, pre-exponential factors scaled by 1e-8 (the calibrated
+mechanism; the literal draw is too stiff to integrate, see the design notes).
+
+Prints one JSON line: FP64 cell-integrations/s as `value`, the mixed-precision figure
+and speed-up beside it, the roofline of the integration kernel (algorithmic FP64
+operations / kernel time against the FP64 vector peak) and the CPU oracle timed on a
+bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ROK4E cell-integrations/s at 53 species, FP64 vs mixed, % of roofline"
+A_SCALE = 1e-8
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def run_gpu(w, precision, steps, warmup, R, torch):
+    from paper_1712_00953_amd import workmodel
+    st = w.states
+    n = st.n_cells
+    dev = torch.device("cuda:0")
+    Y0 = torch.tensor(st.Y, dtype=torch.float64, device=dev)
+    T0 = torch.tensor(st.T, dtype=torch.float64, device=dev)
+    p = torch.tensor(st.p, dtype=torch.float64, device=dev)
+    # one private copy of the inputs per step, made before any timing
+    copies = [(Y0.clone(), T0.clone()) for _ in range(warmup + steps)]
+    m = R.Mech(w.mech, M=w.M, precision=precision, max_attempts=200000)
+    m.reserve(n)
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        m.integrate(copies[i][0], copies[i][1], p, w.dt, w.rtol, w.atol)
+    torch.cuda.synchronize()
+    stats = m.stats()
+    if stats["status_count"][0] != n:
+        raise RuntimeError(f"cells failed: {stats}")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        Yc, Tc = copies[warmup + i]
+        ev[i][0].record(stream)
+        m.integrate(Yc, Tc, p, w.dt, w.rtol, w.atol)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    stats = m.stats()
+    m.close()
+    ops = workmodel.batch_ops(w.mech, w.M, stats["accepted"], stats["rejected"])
+    kavg = float(np.mean(kern_ms)) * 1e-3
+    return dict(wall_s=wall, ms_per_step=wall / steps * 1e3, kernel_s=kavg,
+                cells_per_s=n * steps / wall, attempts=stats["accepted"] + stats["rejected"],
+                accepted=stats["accepted"], rejected=stats["rejected"],
+                max_attempts=stats["max_attempts"], flops=ops["flops"],
+                transcendentals=ops["transcendentals"],
+                tflops=ops["flops"] / kavg * 1e-12,
+                bytes=workmodel.state_bytes(w.mech, n))
+
+
+def run_cpu_baseline(w, target_s=10.0):
+    """The oracle on a uniformly drawn sample of the batch, all host threads."""
+    from oracle import oracle as O
+    st = w.states
+    threads = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(77)
+    pilot = st.subset(np.sort(rng.choice(st.n_cells, 256, replace=False)))
+    t0 = time.perf_counter()
+    O.integrate(w.mech, pilot.Y, pilot.T, pilot.p, w.dt, w.rtol, w.atol, w.M, nthreads=threads)
+    per_cell = (time.perf_counter() - t0) / 256
+    n = int(min(st.n_cells, max(256, target_s / max(per_cell, 1e-9))))
+    idx = np.sort(np.random.default_rng(78).choice(st.n_cells, n, replace=False))
+    sub = st.subset(idx)
+    t0 = time.perf_counter()
+    O.integrate(w.mech, sub.Y, sub.T, sub.p, w.dt, w.rtol, w.atol, w.M, nthreads=threads)
+    el = time.perf_counter() - t0
+    return dict(value=n / el, unit="cell-integrations/s", cores=threads, kind="oracle",
+                sample=f"{n} cells drawn uniformly (seed 78) from the {st.n_cells}-cell batch, "
+                       f"{el:.1f} s wall on {threads} threads of {cpu_model()}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the measurement, copy 1 GiB device-to-device (a plain copy "
+                         "kernel of known size, to scale HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the reaction substep is cell-parallel and "
+              f"this build runs on a single MI355X; --gpus {args.gpus} is not supported.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1712_00953_amd import rok4e as R
+    from paper_1712_00953_amd import synth
+    R.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    w = synth.workload(2, a_scale=A_SCALE)
+    log(f"workload {w.name}: {w.states.n_cells} cells, M={w.M}, dt={w.dt}")
+    fp64 = run_gpu(w, R.FP64, args.steps, args.warmup, R, torch)
+    log(f"fp64: {fp64['cells_per_s']:.4e} cells/s, {fp64['ms_per_step']:.2f} ms/step, "
+        f"{fp64['attempts']} attempts/step, {fp64['tflops']:.3f} TFLOP/s")
+    mixed = None
+    if not args.no_mixed:
+        mixed = run_gpu(w, R.MIXED, args.steps, args.warmup, R, torch)
+        log(f"mixed: {mixed['cells_per_s']:.4e} cells/s, {mixed['ms_per_step']:.2f} ms/step")
+    if args.copy_calibration:
+        # write a 1 GiB buffer, evict it from the caches with a second one, then copy it:
+        # the copy kernel reads 1 GiB and writes 1 GiB
+        x = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        evict = torch.ones_like(x)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 1073741824 bytes read, 1073741824 bytes written "
+            f"(last elementwise kernel), check {float(y[0] + evict[0])}")
+        del x, y, evict
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = run_cpu_baseline(w, args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.4e} cells/s ({cpu['sample']})")
+
+    achieved = fp64["tflops"]
+    out = {
+        "metric": METRIC,
+        "value": fp64["cells_per_s"],
+        "unit": "cell-integrations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fp64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name + " (pre-exponential factors x 1e-8)",
+                   "n_species": w.mech.n_species, "n_reactions": w.mech.n_reactions,
+                   "n_cells": w.states.n_cells, "M": w.M, "dt": w.dt, "rtol": w.rtol,
+                   "atol": w.atol, "a_scale": A_SCALE, "precision": "fp64",
+                   "attempts_per_step": fp64["attempts"], "max_attempts_cell": fp64["max_attempts"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "k_integrate (persistent ROK4E integration)",
+                     "kernel_ms": fp64["kernel_s"] * 1e3,
+                     "algorithmic_flops_per_launch": fp64["flops"],
+                     "transcendentals_per_launch": fp64["transcendentals"],
+                     "state_bytes_per_launch": fp64["bytes"],
+                     "hbm_frac_algorithmic": fp64["bytes"] / fp64["kernel_s"] / 1e9 / PEAK_HBM_GBS},
+    }
+    if mixed is not None:
+        out["mixed"] = {"value": mixed["cells_per_s"], "unit": "cell-integrations/s",
+                        "ms_per_step": mixed["ms_per_step"], "dtype": "f32 rates / f64 state",
+                        "speedup_vs_fp64": mixed["cells_per_s"] / fp64["cells_per_s"],
+                        "attempts_per_step": mixed["attempts"],
+                        "tflops_fp64_equivalent": mixed["tflops"]}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
