@@ -25,9 +25,11 @@ __global__ void k_zero_u32(unsigned int* x) { *x = 0u; }
 template <int L, int ROWS, int MMAX, class RT>
 __global__ void __launch_bounds__(256, 2) k_integrate(DevMech m, Launch P) {
   extern __shared__ __align__(16) char smem[];
+  const MechLds t = load_mech_lds(m, smem);
   const int lane = (int)(threadIdx.x % L);
-  char* seg = smem + (threadIdx.x / L) * P.seg_bytes;
+  char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
   const SegLds<RT> S = seg_lds<RT>(seg, P);
+  init_seg<RT>(m, S);
   while (true) {
     // Every lane takes part in the atomic (the segment's first lane adds 1, the others
     // 0), so no lane-dependent branch surrounds the value that is then broadcast.
@@ -37,7 +39,7 @@ __global__ void __launch_bounds__(256, 2) k_integrate(DevMech m, Launch P) {
     double u[ROWS], s[ROWS], p;
     CellResult r{3, 0, 0};
     if (load_cell<L, ROWS>(m, P, cell, lane, u, s, p)) {
-      r = integrate_cell<L, ROWS, MMAX, RT>(m, P, u, p, s, S, lane);
+      r = integrate_cell<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane);
       store_cell<L, ROWS>(m, P, cell, lane, u);
     }
     // every lane of the segment stores the same (segment-uniform) values
@@ -51,9 +53,11 @@ __global__ void __launch_bounds__(256, 2) k_integrate(DevMech m, Launch P) {
 template <int L, int ROWS, class RT>
 __global__ void __launch_bounds__(256, 2) k_rhs(DevMech m, Launch P, double* dY, double* dT) {
   extern __shared__ __align__(16) char smem[];
+  const MechLds t = load_mech_lds(m, smem);
   const int lane = (int)(threadIdx.x % L);
-  char* seg = smem + (threadIdx.x / L) * P.seg_bytes;
+  char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
   const SegLds<RT> S = seg_lds<RT>(seg, P);
+  init_seg<RT>(m, S);
   const int64_t nseg = (int64_t)gridDim.x * (blockDim.x / L);
   const int64_t n = P.n_cells;
   const int ns = m.ns;
@@ -65,7 +69,7 @@ __global__ void __launch_bounds__(256, 2) k_rhs(DevMech m, Launch P, double* dY,
       u[i] = r < ns ? P.Y[(int64_t)r * n + cell] : (r == ns ? P.T[cell] : 0.0);
     }
     RT w[ROWS];
-    rhs<L, ROWS, RT, false>(m, u, P.p[cell], f, S.r, lane, nullptr, w);
+    rhs<L, ROWS, RT, false>(m, t, u, P.p[cell], f, S.r, lane, nullptr, w);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
       const int r = i * L + lane;
@@ -80,9 +84,11 @@ template <int L, int ROWS, int MMAX, class RT>
 __global__ void __launch_bounds__(256, 2) k_arnoldi(DevMech m, Launch P, double* Qo, double* Ho,
                                                   int32_t* Mo) {
   extern __shared__ __align__(16) char smem[];
+  const MechLds t = load_mech_lds(m, smem);
   const int lane = (int)(threadIdx.x % L);
-  char* seg = smem + (threadIdx.x / L) * P.seg_bytes;
+  char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
   const SegLds<RT> S = seg_lds<RT>(seg, P);
+  init_seg<RT>(m, S);
   const int64_t nseg = (int64_t)gridDim.x * (blockDim.x / L);
   const int64_t n = P.n_cells;
   const int N = m.ns + 1, M = P.M;
@@ -91,11 +97,11 @@ __global__ void __launch_bounds__(256, 2) k_arnoldi(DevMech m, Launch P, double*
     load_cell<L, ROWS>(m, P, cell, lane, u, s, p);
     RhsBase base;
     RT w[ROWS];
-    rhs_forced<L, ROWS, RT, true>(m, u, p, s, fn, S, lane, &base, w);
+    rhs_forced<L, ROWS, RT, true>(m, t, u, p, s, fn, S, lane, &base, w);
     for (int i = 0; i < MMAX * MMAX; ++i) S.H[i] = 0.0;
     lds_sync();
     double Q[ROWS][MMAX];
-    const int Meff = arnoldi<L, ROWS, MMAX, RT>(m, P, u, fn, base, w, Q, S, lane);
+    const int Meff = arnoldi<L, ROWS, MMAX, RT>(m, t, P, u, fn, base, w, Q, S, lane);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
       const int r = i * L + lane;
@@ -152,17 +158,19 @@ using namespace rok4e;
 
 struct rok4e_mech {
   int device = 0;
-  int ns = 0, nr = 0, deg_max = 0;
+  int ns = 0, nr = 0;
   rok4e_options opt{};
   const Variant* var = nullptr;
   int cu_count = 0;
-  // device tables
-  double* d_par = nullptr;    // 6 * nr
-  int4* d_rx = nullptr;
-  double* d_spec = nullptr;   // 3 * ns: W, cp, hf
-  int* d_prod_j = nullptr;
-  int* d_prod_nu = nullptr;
-  int* d_deg = nullptr;
+  size_t lds_per_block_max = 0;
+  // host copy of the mechanism
+  std::vector<double> W, cp, hf, par;          // par: 6 x nr
+  std::vector<int> reac, prod;                 // 2 x nr
+  std::vector<std::vector<std::pair<int, int>>> lists;   // (j, nu) per species
+  // device table image for the current layout
+  int image_lp = -1;
+  DevMech dm{};
+  void* d_image = nullptr;
   unsigned int* d_queue = nullptr;
   // per-cell workspace
   int64_t cap = 0;
@@ -208,93 +216,129 @@ const Variant* pick_variant(int ns, const rok4e_options& o) {
   return best;
 }
 
-// Per-segment LDS: c, dc [ns] and q, kf, kr [nr] in the rate type; H, LU [MMAX^2] FP64;
-// piv [MMAX].
+// Per-segment LDS: c, dc [LP] and the signed rates [2 NRP + 1], kf, kr [NRP] in the rate
+// type; H, LU [MMAX^2], 1/diag(U) [MMAX] in FP64; piv [MMAX].
 struct SegLayout {
-  int bytes, off_dc, off_q, off_kf, off_kr, off_H, off_LU, off_piv;
+  int bytes, off_dc, off_q, off_kf, off_kr, off_H, off_LU, off_rdiag, off_piv;
 };
 
-SegLayout seg_layout(int ns, int nr, const Variant& v) {
+int al16(int x) { return (x + 15) & ~15; }
+
+SegLayout seg_layout(int nr, const Variant& v) {
   const int rt = v.prec == ROK4E_FP64 ? 8 : 4;
-  const int nrr = std::max(nr, 1);
-  auto al = [](int x) { return (x + 15) & ~15; };
+  const int lp = v.L * v.rows;
+  const int nrp = (std::max(nr, 1) + 1) & ~1;
   SegLayout s{};
-  int off = al(ns * rt);
+  int off = al16(lp * rt);
   s.off_dc = off;
-  off = al(off + ns * rt);
+  off = al16(off + lp * rt);
   s.off_q = off;
-  off = al(off + nrr * rt);
+  off = al16(off + (2 * nrp + 1) * rt);
   s.off_kf = off;
-  off = al(off + nrr * rt);
+  off = al16(off + nrp * rt);
   s.off_kr = off;
-  off = al(off + nrr * rt);
+  off = al16(off + nrp * rt);
   s.off_H = off;
-  off = al(off + v.mmax * v.mmax * 8);
+  off = al16(off + v.mmax * v.mmax * 8);
   s.off_LU = off;
-  off = al(off + v.mmax * v.mmax * 8);
+  off = al16(off + v.mmax * v.mmax * 8);
+  s.off_rdiag = off;
+  off = al16(off + v.mmax * 8);
   s.off_piv = off;
-  off = al(off + v.mmax * 4);
+  off = al16(off + v.mmax * 4);
   s.bytes = off;
   return s;
 }
 
-DevMech dev_mech(const rok4e_mech* m) {
-  DevMech d{};
-  d.ns = m->ns;
-  d.nr = m->nr;
-  d.deg_max = m->deg_max;
-  const int nr = m->nr;
-  d.lnAf = m->d_par;
-  d.bf = m->d_par + nr;
-  d.Ef = m->d_par + 2 * nr;
-  d.lnAr = m->d_par + 3 * nr;
-  d.br = m->d_par + 4 * nr;
-  d.Er = m->d_par + 5 * nr;
-  d.rx = m->d_rx;
-  d.W = m->d_spec;
-  d.cp = m->d_spec + m->ns;
-  d.hf = m->d_spec + 2 * m->ns;
-  d.prod_j = m->d_prod_j;
-  d.prod_nu = m->d_prod_nu;
-  d.deg = m->d_deg;
-  return d;
+// Builds (or reuses) the table image for the handle's current layout; see DevMech.
+int ensure_image(rok4e_mech* m) {
+  const int lp = m->var->L * m->var->rows;
+  if (m->image_lp == lp && m->d_image) return ROK4E_OK;
+  const int ns = m->ns, nr = m->nr;
+  const int nrp = (std::max(nr, 1) + 1) & ~1;
+  int D = 0;
+  for (const auto& l : m->lists) {
+    int len = 0;
+    for (const auto& e : l) len += std::abs(e.second);
+    D = std::max(D, len);
+  }
+  D = std::max(8, (D + 7) & ~7);
+  const int off_spec = al16(6 * nrp * 8);
+  const int off_rx = al16(off_spec + 4 * lp * 8);
+  const int off_gidx = al16(off_rx + nrp * 4);
+  const int bytes = al16(off_gidx + D * lp * 4);
+  std::vector<char> img(bytes, 0);
+  double* par = (double*)img.data();
+  for (int q = 0; q < 6; ++q)
+    for (int j = 0; j < nr; ++j) par[q * nrp + j] = m->par[q * nr + j];
+  double* sp = (double*)(img.data() + off_spec);
+  for (int r = 0; r < lp; ++r) {
+    const bool spc = r < ns;
+    sp[r] = spc ? m->W[r] : 1.0;
+    sp[lp + r] = spc ? 1.0 / m->W[r] : 0.0;
+    sp[2 * lp + r] = spc ? m->cp[r] : 0.0;
+    sp[3 * lp + r] = spc ? m->hf[r] : 0.0;
+  }
+  int* rx = (int*)(img.data() + off_rx);
+  for (int j = 0; j < nr; ++j) {
+    int packed = 0;
+    const int sl[4] = {m->reac[2 * j], m->reac[2 * j + 1], m->prod[2 * j], m->prod[2 * j + 1]};
+    for (int a = 0; a < 4; ++a) packed |= (sl[a] < 0 ? ns : sl[a]) << (8 * a);
+    rx[j] = packed;
+  }
+  int* g = (int*)(img.data() + off_gidx);
+  for (int r = 0; r < lp; ++r) {
+    int d = 0;
+    if (r < ns)
+      for (const auto& e : m->lists[r])
+        for (int c = 0; c < std::abs(e.second); ++c) g[(d++) * lp + r] = e.second > 0 ? e.first : nrp + e.first;
+    for (; d < D; ++d) g[d * lp + r] = 2 * nrp;
+  }
+  if (m->d_image) (void)hipFree(m->d_image);
+  m->d_image = nullptr;
+  hipError_t e = hipMalloc(&m->d_image, bytes);
+  if (e == hipSuccess) e = hipMemcpy(m->d_image, img.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e);
+  m->dm = DevMech{ns, nr, nrp, lp, D, off_spec, off_rx, off_gidx, bytes, (const int4*)m->d_image};
+  m->image_lp = lp;
+  return ROK4E_OK;
 }
 
 struct LaunchShape {
   int block, grid, segs_per_block, lds;
 };
 
-int waves_per_block_for(const rok4e_mech* m) {
-  return m->opt.waves_per_block > 0 ? m->opt.waves_per_block : 4;
-}
-
-LaunchShape shape_for(const rok4e_mech* m, const SegLayout& sl, int64_t n_cells, const void* kernel,
-                      bool persistent) {
-  LaunchShape s{};
+// Launch shape: blocks of `waves_per_block` waves (fewer if the block's LDS would not
+// fit), as many blocks per CU as occupancy allows for a persistent launch, never more
+// segments than cells.
+int shape_for(const rok4e_mech* m, const SegLayout& sl, int64_t n_cells, const void* kernel,
+              bool persistent, LaunchShape* out) {
   const Variant& v = *m->var;
-  int wpb = waves_per_block_for(m);
+  int wpb = m->opt.waves_per_block > 0 ? m->opt.waves_per_block : 4;
+  const int segs_per_wave = 64 / v.L;
+  while (wpb > 1 && (size_t)(m->dm.image_bytes + wpb * segs_per_wave * sl.bytes) > m->lds_per_block_max) --wpb;
+  LaunchShape s{};
   s.block = 64 * wpb;
-  s.segs_per_block = s.block / v.L;
-  s.lds = s.segs_per_block * sl.bytes;
+  s.segs_per_block = wpb * segs_per_wave;
+  s.lds = m->dm.image_bytes + s.segs_per_block * sl.bytes;
+  if ((size_t)s.lds > m->lds_per_block_max) return ROK4E_ENOTSUP;
   const int64_t need = (n_cells + s.segs_per_block - 1) / s.segs_per_block;
   int per_cu = 1;
-  if (persistent) {
-    if (m->opt.blocks_per_cu > 0) {
-      per_cu = m->opt.blocks_per_cu;
-    } else {
-      int occ = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, s.block, s.lds) != hipSuccess || occ < 1)
-        occ = 1;
-      per_cu = occ;
-    }
+  if (persistent && m->opt.blocks_per_cu > 0) {
+    per_cu = m->opt.blocks_per_cu;
   } else {
-    per_cu = 8;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, s.block, s.lds) != hipSuccess || occ < 1)
+      occ = 1;
+    per_cu = occ;
   }
   int64_t grid = (int64_t)per_cu * m->cu_count;
+  if (!persistent) grid = std::min<int64_t>(grid * 4, need);
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
   s.grid = (int)grid;
-  return s;
+  *out = s;
+  return ROK4E_OK;
 }
 
 int ensure_workspace(rok4e_mech* m, int64_t n, hipStream_t stream) {
@@ -338,6 +382,7 @@ Launch base_launch(rok4e_mech* m, int64_t n, double* Y, double* T, const double*
   P.off_kr = sl.off_kr;
   P.off_H = sl.off_H;
   P.off_LU = sl.off_LU;
+  P.off_rdiag = sl.off_rdiag;
   P.off_piv = sl.off_piv;
   return P;
 }
@@ -372,8 +417,7 @@ int rok4e_mech_destroy(rok4e_mech* m) {
   (void)hipGetDevice(&dev);
   (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
-  void* bufs[] = {m->d_par, m->d_rx, m->d_spec, m->d_prod_j, m->d_prod_nu, m->d_deg,
-                  m->d_queue, m->d_acc, m->d_rej, m->d_status};
+  void* bufs[] = {m->d_image, m->d_queue, m->d_acc, m->d_rej, m->d_status};
   for (void* b : bufs) (void)hipFree(b);
   (void)hipSetDevice(dev);
   delete m;
@@ -405,12 +449,31 @@ int rok4e_mech_create(const rok4e_mech_desc* d, const rok4e_options* o, rok4e_me
     }
     if (d->reac[2 * j] < 0 || d->prod[2 * j] < 0) return ROK4E_EINVAL;   // first slot filled
   }
+  if (ns > 254) return ROK4E_ENOTSUP;
   const Variant* var = pick_variant(ns, opt);
   if (!var) return ROK4E_ENOTSUP;
 
+  rok4e_mech* m = new (std::nothrow) rok4e_mech();
+  if (!m) return ROK4E_ENOMEM;
+  (void)hipGetDevice(&m->device);
+  m->ns = ns;
+  m->nr = nr;
+  m->opt = opt;
+  m->var = var;
+  m->W.assign(d->W, d->W + ns);
+  m->cp.assign(d->cp, d->cp + ns);
+  m->hf.assign(d->hf, d->hf + ns);
+  m->par.assign((size_t)6 * nr, 0.0);
+  const double* src[6] = {d->lnAf, d->bf, d->Ef, d->lnAr, d->br, d->Er};
+  for (int q = 0; q < 6; ++q)
+    for (int j = 0; j < nr; ++j) m->par[(size_t)q * nr + j] = src[q][j];
+  if (nr > 0) {
+    m->reac.assign(d->reac, d->reac + 2 * nr);
+    m->prod.assign(d->prod, d->prod + 2 * nr);
+  }
   // Species-major production lists: for species k, (reaction j, net coefficient) for
   // every reaction with a non-zero net coefficient, in increasing j.
-  std::vector<std::vector<std::pair<int, int>>> lists(ns);
+  m->lists.assign(ns, {});
   for (int j = 0; j < nr; ++j) {
     int sp[4], nu[4], nsp = 0;
     auto add = [&](int r, int c) {
@@ -425,67 +488,19 @@ int rok4e_mech_create(const rok4e_mech_desc* d, const rok4e_options* o, rok4e_me
     add(d->prod[2 * j], +1);
     add(d->prod[2 * j + 1], +1);
     for (int i = 0; i < nsp; ++i)
-      if (nu[i] != 0) lists[sp[i]].push_back({j, nu[i]});
+      if (nu[i] != 0) m->lists[sp[i]].push_back({j, nu[i]});
   }
-  int deg_max = 0;
-  for (auto& l : lists) deg_max = std::max<int>(deg_max, (int)l.size());
-  const int dmax = std::max(deg_max, 1);
-  std::vector<int> pj((size_t)dmax * ns, 0), pn((size_t)dmax * ns, 0), deg(ns, 0);
-  for (int k = 0; k < ns; ++k) {
-    deg[k] = (int)lists[k].size();
-    for (int i = 0; i < deg[k]; ++i) {
-      pj[(size_t)i * ns + k] = lists[k][i].first;
-      pn[(size_t)i * ns + k] = lists[k][i].second;
-    }
-  }
-  std::vector<double> par((size_t)6 * std::max(nr, 1), 0.0);
-  std::vector<int4> rx(std::max(nr, 1));
-  for (int j = 0; j < nr; ++j) {
-    par[j] = d->lnAf[j];
-    par[nr + j] = d->bf[j];
-    par[2 * nr + j] = d->Ef[j];
-    par[3 * nr + j] = d->lnAr[j];
-    par[4 * nr + j] = d->br[j];
-    par[5 * nr + j] = d->Er[j];
-    rx[j] = make_int4(d->reac[2 * j], d->reac[2 * j + 1], d->prod[2 * j], d->prod[2 * j + 1]);
-  }
-  std::vector<double> spec((size_t)3 * ns);
-  for (int k = 0; k < ns; ++k) {
-    spec[k] = d->W[k];
-    spec[ns + k] = d->cp[k];
-    spec[2 * ns + k] = d->hf[k];
-  }
-
-  rok4e_mech* m = new (std::nothrow) rok4e_mech();
-  if (!m) return ROK4E_ENOMEM;
-  (void)hipGetDevice(&m->device);
-  m->ns = ns;
-  m->nr = nr;
-  m->deg_max = deg_max;
-  m->opt = opt;
-  m->var = var;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, m->device) != hipSuccess) {
     delete m;
     return ROK4E_EHIP;
   }
   m->cu_count = prop.multiProcessorCount;
-  hipError_t e = hipSuccess;
-  auto up = [&](void** dst, const void* src, size_t bytes) {
-    if (e != hipSuccess) return;
-    e = hipMalloc(dst, bytes);
-    if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-  };
-  up((void**)&m->d_par, par.data(), par.size() * sizeof(double));
-  up((void**)&m->d_rx, rx.data(), rx.size() * sizeof(int4));
-  up((void**)&m->d_spec, spec.data(), spec.size() * sizeof(double));
-  up((void**)&m->d_prod_j, pj.data(), pj.size() * sizeof(int));
-  up((void**)&m->d_prod_nu, pn.data(), pn.size() * sizeof(int));
-  up((void**)&m->d_deg, deg.data(), deg.size() * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc((void**)&m->d_queue, sizeof(unsigned int));
+  m->lds_per_block_max = prop.sharedMemPerBlock;
+  hipError_t e = hipMalloc((void**)&m->d_queue, sizeof(unsigned int));
   if (e == hipSuccess) e = hipMemset(m->d_queue, 0, sizeof(unsigned int));
-  if (e != hipSuccess) {
-    const int rc = hip_fail(e);
+  int rc = e == hipSuccess ? ensure_image(m) : hip_fail(e);
+  if (rc != ROK4E_OK) {
     rok4e_mech_destroy(m);
     return rc;
   }
@@ -499,7 +514,7 @@ int rok4e_set_options(rok4e_mech* m, const rok4e_options* o) {
   if (!var) return ROK4E_ENOTSUP;
   m->opt = *o;
   m->var = var;
-  return ROK4E_OK;
+  return ensure_image(m);
 }
 
 int rok4e_get_options(const rok4e_mech* m, rok4e_options* o) {
@@ -536,15 +551,16 @@ int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
   hipStream_t st = (hipStream_t)stream;
   rc = ensure_workspace(m, n_cells, st);
   if (rc) return rc;
-  const SegLayout sl = seg_layout(m->ns, m->nr, *m->var);
+  const SegLayout sl = seg_layout(m->nr, *m->var);
   Launch P = base_launch(m, n_cells, Y, T, p, S, sl);
   P.dt = dt;
   P.rtol = rtol;
   P.atol = atol;
-  const DevMech dm = dev_mech(m);
-  const LaunchShape sh = shape_for(m, sl, n_cells, (const void*)m->var->integrate, true);
+  LaunchShape sh;
+  rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate, true, &sh);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
-  hipLaunchKernelGGL(m->var->integrate, dim3(sh.grid), dim3(sh.block), sh.lds, st, dm, P);
+  hipLaunchKernelGGL(m->var->integrate, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e);
   m->last_n = n_cells;
@@ -562,11 +578,12 @@ int rok4e_rhs(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T, 
   if (rc) return rc;
   if (n_cells > 0 && (!dY || !dT)) return ROK4E_EINVAL;
   if (n_cells == 0) return ROK4E_OK;
-  const SegLayout sl = seg_layout(m->ns, m->nr, *m->var);
+  const SegLayout sl = seg_layout(m->nr, *m->var);
   Launch P = base_launch(m, n_cells, const_cast<double*>(Y), const_cast<double*>(T), p, nullptr, sl);
-  const LaunchShape sh = shape_for(m, sl, n_cells, (const void*)m->var->rhs, false);
-  hipLaunchKernelGGL(m->var->rhs, dim3(sh.grid), dim3(sh.block), sh.lds, (hipStream_t)stream, dev_mech(m), P,
-                     dY, dT);
+  LaunchShape sh;
+  rc = shape_for(m, sl, n_cells, (const void*)m->var->rhs, false, &sh);
+  if (rc) return rc;
+  hipLaunchKernelGGL(m->var->rhs, dim3(sh.grid), dim3(sh.block), sh.lds, (hipStream_t)stream, m->dm, P, dY, dT);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? ROK4E_OK : hip_fail(e);
 }
@@ -577,11 +594,13 @@ int rok4e_arnoldi(int64_t n_cells, rok4e_mech* m, const double* Y, const double*
   if (rc) return rc;
   if (n_cells > 0 && (!Q || !H || !Meff)) return ROK4E_EINVAL;
   if (n_cells == 0) return ROK4E_OK;
-  const SegLayout sl = seg_layout(m->ns, m->nr, *m->var);
+  const SegLayout sl = seg_layout(m->nr, *m->var);
   Launch P = base_launch(m, n_cells, const_cast<double*>(Y), const_cast<double*>(T), p, nullptr, sl);
-  const LaunchShape sh = shape_for(m, sl, n_cells, (const void*)m->var->arnoldi, false);
-  hipLaunchKernelGGL(m->var->arnoldi, dim3(sh.grid), dim3(sh.block), sh.lds, (hipStream_t)stream, dev_mech(m),
-                     P, Q, H, Meff);
+  LaunchShape sh;
+  rc = shape_for(m, sl, n_cells, (const void*)m->var->arnoldi, false, &sh);
+  if (rc) return rc;
+  hipLaunchKernelGGL(m->var->arnoldi, dim3(sh.grid), dim3(sh.block), sh.lds, (hipStream_t)stream, m->dm, P, Q, H,
+                     Meff);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? ROK4E_OK : hip_fail(e);
 }

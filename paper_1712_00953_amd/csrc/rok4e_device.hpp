@@ -31,16 +31,29 @@ constexpr double BH1 = -0.217819895945721, BH2 = 1.03130847478467, BH3 = 0.18651
 // Embedded minus main weights (b3 = 0, bh4 = 0).
 constexpr double E1 = BH1 - B1, E2 = BH2 - B2, E3 = BH3 - 0.0, E4 = 0.0 - B4;
 
-// Device view of a mechanism.
+// Device view of a mechanism: one contiguous table image in global memory, copied to
+// LDS once per block by the kernels.  Image layout (NRP = reaction count rounded to even,
+// LP = lanes x slots of the layout, D = production-list length):
+//   double par[6][NRP]   ln A_f, b_f, E_f, ln A_r, b_r, E_r
+//   double spec[4][LP]   W, 1/W, c_p, h_f per state row (zeros/ones past the species)
+//   int    rx[NRP]       species of reaction j packed in bytes (reac0, reac1, prod0,
+//                        prod1); an absent slot holds ns, whose concentration is 1
+//   int    gidx[D][LP]   production list of row r: indices into the signed rates
+//                        qs = (q_0..q_{NRP-1}, -q_0..-q_{NRP-1}, 0); a coefficient of
+//                        +-2 appears as two entries, padding points at the final 0
 struct DevMech {
-  int ns, nr, deg_max;
+  int ns, nr, nrp, lp, D;
+  int off_spec, off_rx, off_gidx, image_bytes;
+  const int4* image;
+};
+
+// LDS view of the table image.
+struct MechLds {
   const double* lnAf; const double* bf; const double* Ef;
   const double* lnAr; const double* br; const double* Er;
-  const int4* rx;           // (reac0, reac1, prod0, prod1), -1 if absent
-  const double* W; const double* cp; const double* hf;
-  const int* prod_j;        // [deg_max][ns] reaction index of the d-th production term
-  const int* prod_nu;       // [deg_max][ns] net stoichiometric coefficient
-  const int* deg;           // [ns] number of production terms of species k
+  const double* W; const double* invW; const double* cp; const double* hf;
+  const int* rx;
+  const int* gidx;
 };
 
 // Per-launch arguments of the integrator.
@@ -51,8 +64,25 @@ struct Launch {
   int M, max_attempts, fixed_steps;
   unsigned int* queue;
   int32_t* acc; int32_t* rej; int32_t* status;
-  int seg_bytes, off_dc, off_q, off_kf, off_kr, off_H, off_LU, off_piv;
+  int seg_bytes, off_dc, off_q, off_kf, off_kr, off_H, off_LU, off_rdiag, off_piv;
 };
+
+// Copies the table image to the start of the block's LDS and returns the view.  All
+// threads of the block take part; ends with a block barrier (kernel start only).
+__device__ __forceinline__ MechLds load_mech_lds(const DevMech& m, char* lds) {
+  int4* dst = (int4*)lds;
+  for (int i = threadIdx.x; i < m.image_bytes / 16; i += blockDim.x) dst[i] = m.image[i];
+  __syncthreads();
+  const double* par = (const double*)lds;
+  MechLds t;
+  t.lnAf = par; t.bf = par + m.nrp; t.Ef = par + 2 * m.nrp;
+  t.lnAr = par + 3 * m.nrp; t.br = par + 4 * m.nrp; t.Er = par + 5 * m.nrp;
+  const double* sp = (const double*)(lds + m.off_spec);
+  t.W = sp; t.invW = sp + m.lp; t.cp = sp + 2 * m.lp; t.hf = sp + 3 * m.lp;
+  t.rx = (const int*)(lds + m.off_rx);
+  t.gidx = (const int*)(lds + m.off_gidx);
+  return t;
+}
 
 // ------------------------------------------------------------ cross-lane ----
 
@@ -154,16 +184,16 @@ __device__ __forceinline__ bool finite_(V x) { return __builtin_isfinite(x); }
 // Per-segment LDS scratch of the right-hand side.
 template <class RT>
 struct RhsLds {
-  RT* c;    // [ns] concentrations of the base state
-  RT* dc;   // [ns] their increments (difference evaluation)
-  RT* q;    // [nr] rates of progress, or their increments
-  RT* kf;   // [nr] forward rate constants of the base state
-  RT* kr;   // [nr] reverse rate constants of the base state
+  RT* c;    // [LP] concentrations of the base state; c[ns] = 1 (absent reaction slot)
+  RT* dc;   // [LP] their increments (difference evaluation); dc[ns] = 0
+  RT* qs;   // [2 NRP + 1] signed rates of progress (or increments), last entry 0
+  RT* kf;   // [NRP] forward rate constants of the base state
+  RT* kr;   // [NRP] reverse rate constants of the base state
 };
 
 // Cell-uniform quantities of a base evaluation f(u), kept for the difference evaluation.
 struct RhsBase {
-  double T, sigma, cpbar, rho, hsum;
+  double T, invT, sigma, cpbar, rho, invrho, hsum;
 };
 
 // expm1 for the small arguments of the difference evaluation (Taylor series to x^5,
@@ -183,6 +213,17 @@ __device__ __forceinline__ double row_value(const double (&u)[ROWS], int slot) {
   return v;
 }
 
+// Sum of the signed rates listed for state row r (fixed order: increasing reaction
+// index), i.e. sum_j nu_rj q_j.
+template <class RT>
+__device__ __forceinline__ RT production(const MechLds& t, const RT* qs, int D, int lp, int r) {
+  const int* g = t.gidx + r;
+  RT acc = 0;
+#pragma unroll 8
+  for (int d = 0; d < D; ++d) acc = acc + qs[g[d * lp]];
+  return acc;
+}
+
 // f(u) of one cell held by a segment (Sec. 4.4, e:cv_reactor, constant-pressure
 // reading): rho = p / (Ru T sum Y/W), c_k = 1e-6 rho Y_k / W_k (mol/cm^3),
 // q_j = k_f prod c - k_r prod c, omega_k = 1e6 sum_j nu_kj q_j,
@@ -190,75 +231,63 @@ __device__ __forceinline__ double row_value(const double (&u)[ROWS], int slot) {
 // RT is the type of the rate constants, concentrations and production sums.  With SAVE
 // the rate constants go to LDS and the base quantities to *base / w for rhs_diff.
 template <int L, int ROWS, class RT, bool SAVE>
-__device__ __forceinline__ void rhs(const DevMech& m, const double (&u)[ROWS], double p,
-                                    double (&f)[ROWS], const RhsLds<RT>& S, int lane,
+__device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const double (&u)[ROWS],
+                                    double p, double (&f)[ROWS], const RhsLds<RT>& S, int lane,
                                     RhsBase* base, RT (&w)[ROWS]) {
-  const int ns = m.ns;
+  const int ns = m.ns, nrp = m.nrp;
   const int sT = ns / L, lT = ns % L;
   const double T = seg_bcast<L>(row_value<L, ROWS>(u, sT), lT);
 
   double ps[ROWS], pc[ROWS];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
-    const int r = s * L + lane;
-    ps[s] = 0.0;
-    pc[s] = 0.0;
-    if (r < ns) {
-      ps[s] = u[s] / m.W[r];
-      pc[s] = u[s] * m.cp[r];
-    }
+    const int r = s * L + lane;          // rows past the species have invW = cp = 0
+    ps[s] = (r < ns ? u[s] : 0.0) * t.invW[r];
+    pc[s] = (r < ns ? u[s] : 0.0) * t.cp[r];
   }
   const double sigma = seg_sum<L, ROWS>(ps);
   const double cpbar = seg_sum<L, ROWS>(pc);
   const double rho = p / (kRu * T * sigma);
+  const double invrho = 1.0 / rho;
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    if (r < ns) S.c[r] = (RT)(1e-6 * rho * u[s] / m.W[r]);
+    if (r < ns) S.c[r] = (RT)(1e-6 * rho * u[s] * t.invW[r]);
   }
   const double lnT = log(T);
   const double invRT = 1.0 / (kRu * T);
   lds_sync();
   for (int j = lane; j < m.nr; j += L) {
-    const RT kf = arrhenius(m.lnAf[j], m.bf[j], m.Ef[j], lnT, invRT, RT(0));
-    const RT kr = arrhenius(m.lnAr[j], m.br[j], m.Er[j], lnT, invRT, RT(0));
+    const RT kf = arrhenius(t.lnAf[j], t.bf[j], t.Ef[j], lnT, invRT, RT(0));
+    const RT kr = arrhenius(t.lnAr[j], t.br[j], t.Er[j], lnT, invRT, RT(0));
     if constexpr (SAVE) {
       S.kf[j] = kf;
       S.kr[j] = kr;
     }
-    const int4 ix = m.rx[j];
-    RT pf = S.c[ix.x];
-    if (ix.y >= 0) pf = pf * S.c[ix.y];
-    RT pr = S.c[ix.z];
-    if (ix.w >= 0) pr = pr * S.c[ix.w];
-    S.q[j] = kf * pf - kr * pr;
+    const int x = t.rx[j];
+    const RT pf = S.c[x & 0xFF] * S.c[(x >> 8) & 0xFF];
+    const RT pr = S.c[(x >> 16) & 0xFF] * S.c[(x >> 24) & 0xFF];
+    const RT q = kf * pf - kr * pr;
+    S.qs[j] = q;
+    S.qs[nrp + j] = -q;
   }
   lds_sync();
   double ph[ROWS];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    ph[s] = 0.0;
-    f[s] = 0.0;
-    w[s] = 0;
-    if (r < ns) {
-      RT acc = 0;
-      const int dg = m.deg[r];
-      for (int d = 0; d < dg; ++d)
-        acc = acc + (RT)m.prod_nu[d * ns + r] * S.q[m.prod_j[d * ns + r]];
-      const RT wk = (RT)1e6 * acc;
-      w[s] = wk;
-      f[s] = (double)((RT)m.W[r] * wk / (RT)rho);
-      const RT hk = (RT)(m.hf[r] + m.cp[r] * (T - kTref));
-      ph[s] = (double)(hk * (RT)m.W[r] * wk);
-    }
+    const RT wk = (RT)1e6 * production<RT>(t, S.qs, m.D, m.lp, r);
+    w[s] = wk;
+    f[s] = (double)((RT)t.W[r] * wk * (RT)invrho);
+    const RT hk = (RT)(t.hf[r] + t.cp[r] * (T - kTref));
+    ph[s] = (double)(hk * (RT)t.W[r] * wk);
   }
   const double hsum = seg_sum<L, ROWS>(ph);
   const double fT = -hsum / (rho * cpbar);
 #pragma unroll
   for (int s = 0; s < ROWS; ++s)
     if (s == sT && lane == lT) f[s] = fT;
-  if constexpr (SAVE) *base = RhsBase{T, sigma, cpbar, rho, hsum};
+  if constexpr (SAVE) *base = RhsBase{T, 1.0 / T, sigma, cpbar, rho, invrho, hsum};
   lds_sync();   // the LDS scratch is reused by the next evaluation
 }
 
@@ -268,10 +297,11 @@ __device__ __forceinline__ void rhs(const DevMech& m, const double (&u)[ROWS], d
 // instead of the absolute accuracy eps |f| of a difference of two evaluations.
 // The increments of the scalar state functions (rho, ln T, 1/(Ru T)) are FP64.
 template <int L, int ROWS, class RT>
-__device__ __forceinline__ void rhs_diff(const DevMech& m, const RhsBase& B, const RT (&w)[ROWS],
-                                         const double (&u)[ROWS], const double (&du)[ROWS],
-                                         double (&df)[ROWS], const RhsLds<RT>& S, int lane) {
-  const int ns = m.ns;
+__device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, const RhsBase& B,
+                                         const RT (&w)[ROWS], const double (&u)[ROWS],
+                                         const double (&du)[ROWS], double (&df)[ROWS],
+                                         const RhsLds<RT>& S, int lane) {
+  const int ns = m.ns, nrp = m.nrp;
   const int sT = ns / L, lT = ns % L;
   const double T = B.T;
   const double dT = seg_bcast<L>(row_value<L, ROWS>(du, sT), lT);
@@ -280,12 +310,8 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const RhsBase& B, con
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    ps[s] = 0.0;
-    pc[s] = 0.0;
-    if (r < ns) {
-      ps[s] = du[s] / m.W[r];
-      pc[s] = du[s] * m.cp[r];
-    }
+    ps[s] = (r < ns ? du[s] : 0.0) * t.invW[r];
+    pc[s] = (r < ns ? du[s] : 0.0) * t.cp[r];
   }
   const double dsigma = seg_sum<L, ROWS>(ps);
   const double dcp = seg_sum<L, ROWS>(pc);
@@ -293,51 +319,39 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const RhsBase& B, con
   const double rho = B.rho;
   const double drho = -rho * (dT * sigma1 + T * dsigma) / (T1 * sigma1);
   const double rho1 = rho + drho;
+  const double invrho1 = 1.0 / rho1;
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    if (r < ns) S.dc[r] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) / m.W[r]);
+    if (r < ns) S.dc[r] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * t.invW[r]);
   }
-  const double dlnT = log1p(dT / T);
+  const double dlnT = log1p(dT * B.invT);
   const double dinvRT = -dT / (kRu * T * T1);
   lds_sync();
   for (int j = lane; j < m.nr; j += L) {
     const RT kf = S.kf[j], kr = S.kr[j];
-    const RT dkf = kf * (RT)expm1_small(m.bf[j] * dlnT - m.Ef[j] * dinvRT);
-    const RT dkr = kr * (RT)expm1_small(m.br[j] * dlnT - m.Er[j] * dinvRT);
-    const int4 ix = m.rx[j];
+    const RT dkf = kf * (RT)expm1_small(t.bf[j] * dlnT - t.Ef[j] * dinvRT);
+    const RT dkr = kr * (RT)expm1_small(t.br[j] * dlnT - t.Er[j] * dinvRT);
+    const int x = t.rx[j];
     // products of concentrations with increments: d(ab) = (a + da) db + da b
-    RT pf = S.c[ix.x], dpf = S.dc[ix.x];
-    if (ix.y >= 0) {
-      const RT cb = S.c[ix.y], dcb = S.dc[ix.y];
-      dpf = (pf + dpf) * dcb + dpf * cb;
-      pf = pf * cb;
-    }
-    RT pr = S.c[ix.z], dpr = S.dc[ix.z];
-    if (ix.w >= 0) {
-      const RT cb = S.c[ix.w], dcb = S.dc[ix.w];
-      dpr = (pr + dpr) * dcb + dpr * cb;
-      pr = pr * cb;
-    }
-    S.q[j] = ((kf + dkf) * dpf + dkf * pf) - ((kr + dkr) * dpr + dkr * pr);
+    const int a0 = x & 0xFF, a1 = (x >> 8) & 0xFF, b0 = (x >> 16) & 0xFF, b1 = (x >> 24) & 0xFF;
+    const RT ca = S.c[a0], dca = S.dc[a0], cb = S.c[a1], dcb = S.dc[a1];
+    const RT pf = ca * cb, dpf = (ca + dca) * dcb + dca * cb;
+    const RT cc = S.c[b0], dcc = S.dc[b0], cd = S.c[b1], dcd = S.dc[b1];
+    const RT pr = cc * cd, dpr = (cc + dcc) * dcd + dcc * cd;
+    const RT dq = ((kf + dkf) * dpf + dkf * pf) - ((kr + dkr) * dpr + dkr * pr);
+    S.qs[j] = dq;
+    S.qs[nrp + j] = -dq;
   }
   lds_sync();
   double ph[ROWS];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    ph[s] = 0.0;
-    df[s] = 0.0;
-    if (r < ns) {
-      RT acc = 0;
-      const int dg = m.deg[r];
-      for (int d = 0; d < dg; ++d)
-        acc = acc + (RT)m.prod_nu[d * ns + r] * S.q[m.prod_j[d * ns + r]];
-      const double dw = 1e6 * (double)acc, wk = (double)w[s];
-      df[s] = m.W[r] * (dw / rho1 - wk * drho / (rho * rho1));
-      const double hk = m.hf[r] + m.cp[r] * (T - kTref), dhk = m.cp[r] * dT;
-      ph[s] = m.W[r] * ((hk + dhk) * dw + dhk * wk);
-    }
+    const double dw = 1e6 * (double)production<RT>(t, S.qs, m.D, m.lp, r), wk = (double)w[s];
+    df[s] = t.W[r] * (dw * invrho1 - wk * drho * B.invrho * invrho1);
+    const double hk = t.hf[r] + t.cp[r] * (T - kTref), dhk = t.cp[r] * dT;
+    ph[s] = t.W[r] * ((hk + dhk) * dw + dhk * wk);
   }
   const double dhsum = seg_sum<L, ROWS>(ph);
   const double D = rho * B.cpbar, dD = drho * cp1 + rho * dcp;

@@ -10,9 +10,10 @@ namespace rok4e {
 template <class RT>
 struct SegLds {
   RhsLds<RT> r;
-  double* H;   // [MMAX * MMAX] Hessenberg matrix of the Arnoldi process
-  double* LU;  // [MMAX * MMAX] factors of I - h gamma H
-  int* piv;    // [MMAX]
+  double* H;      // [MMAX * MMAX] Hessenberg matrix of the Arnoldi process
+  double* LU;     // [MMAX * MMAX] factors of I - h gamma H
+  double* rdiag;  // [MMAX] reciprocals of the diagonal of U
+  int* piv;       // [MMAX]
 };
 
 template <class RT>
@@ -22,17 +23,28 @@ __device__ __forceinline__ SegLds<RT> seg_lds(char* seg, const Launch& P) {
                    (RT*)(seg + P.off_kr)};
   S.H = (double*)(seg + P.off_H);
   S.LU = (double*)(seg + P.off_LU);
+  S.rdiag = (double*)(seg + P.off_rdiag);
   S.piv = (int*)(seg + P.off_piv);
   return S;
 }
 
+// Constant entries of the segment's scratch: the concentration of an absent reaction
+// slot (1, increment 0) and the zero entry of the signed rates.
+template <class RT>
+__device__ __forceinline__ void init_seg(const DevMech& m, const SegLds<RT>& S) {
+  S.r.c[m.ns] = (RT)1;
+  S.r.dc[m.ns] = (RT)0;
+  S.r.qs[2 * m.nrp] = (RT)0;
+  lds_sync();
+}
+
 // f(u) + s for the rows this lane holds (SAVE keeps the base quantities for rhs_diff).
 template <int L, int ROWS, class RT, bool SAVE>
-__device__ __forceinline__ void rhs_forced(const DevMech& m, const double (&u)[ROWS], double p,
-                                           const double (&s)[ROWS], double (&f)[ROWS],
+__device__ __forceinline__ void rhs_forced(const DevMech& m, const MechLds& t, const double (&u)[ROWS],
+                                           double p, const double (&s)[ROWS], double (&f)[ROWS],
                                            const SegLds<RT>& S, int lane, RhsBase* base,
                                            RT (&w)[ROWS]) {
-  rhs<L, ROWS, RT, SAVE>(m, u, p, f, S.r, lane, base, w);
+  rhs<L, ROWS, RT, SAVE>(m, t, u, p, f, S.r, lane, base, w);
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) f[i] = f[i] + s[i];
 }
@@ -43,7 +55,8 @@ __device__ __forceinline__ void rhs_forced(const DevMech& m, const double (&u)[R
 // (LDS) the M x M Hessenberg matrix; both FP64.  Returns M_eff.  Needs the base
 // evaluation of f at u (rhs with SAVE) just before.
 template <int L, int ROWS, int MMAX, class RT>
-__device__ __forceinline__ int arnoldi(const DevMech& m, const Launch& P, const double (&u)[ROWS],
+__device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const Launch& P,
+                                       const double (&u)[ROWS],
                                        const double (&fn)[ROWS], const RhsBase& B, const RT (&w)[ROWS],
                                        double (&Q)[ROWS][MMAX], const SegLds<RT>& S, int lane) {
   const int N = m.ns + 1;
@@ -68,7 +81,7 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const Launch& P, const 
     double du[ROWS], d[ROWS], wv[ROWS];
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) du[i] = delta * Q[i][j];
-    rhs_diff<L, ROWS, RT>(m, B, w, u, du, d, S.r, lane);
+    rhs_diff<L, ROWS, RT>(m, t, B, w, u, du, d, S.r, lane);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) wv[i] = d[i] / delta;
     double wn0 = 0.0;
@@ -109,7 +122,7 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const Launch& P, const 
 // only pivot candidates of column k).  Every lane of the segment computes and writes the
 // same values, so no lane-dependent branch is needed.
 template <int MMAX>
-__device__ __forceinline__ bool lu_factor(double* a, int* piv, int m) {
+__device__ __forceinline__ bool lu_factor(double* a, double* rdiag, int* piv, int m) {
   for (int k = 0; k < m; ++k) {
     int pk = k;
     if (k + 1 < m && fabs(a[(k + 1) * MMAX + k]) > fabs(a[k * MMAX + k])) pk = k + 1;
@@ -125,8 +138,10 @@ __device__ __forceinline__ bool lu_factor(double* a, int* piv, int m) {
     lds_sync();
     const double akk = a[k * MMAX + k];
     if (akk == 0.0) return false;
+    const double rk = 1.0 / akk;
+    rdiag[k] = rk;
     if (k + 1 < m) {
-      const double l = a[(k + 1) * MMAX + k] / akk;
+      const double l = a[(k + 1) * MMAX + k] * rk;
       for (int j = k + 1; j < m; ++j) {
         const double v = a[(k + 1) * MMAX + j] - l * a[k * MMAX + j];
         a[(k + 1) * MMAX + j] = v;
@@ -140,7 +155,8 @@ __device__ __forceinline__ bool lu_factor(double* a, int* piv, int m) {
 
 // x <- (I - h gamma H)^{-1} x for a uniform vector x (all row interchanges first).
 template <int MMAX>
-__device__ __forceinline__ void lu_solve(const double* a, const int* piv, int m, double (&x)[MMAX]) {
+__device__ __forceinline__ void lu_solve(const double* a, const double* rdiag, const int* piv, int m,
+                                         double (&x)[MMAX]) {
 #pragma unroll
   for (int k = 0; k < MMAX - 1; ++k) {
     if (k >= m) break;
@@ -162,7 +178,7 @@ __device__ __forceinline__ void lu_solve(const double* a, const int* piv, int m,
 #pragma unroll
       for (int j = i + 1; j < MMAX; ++j)
         if (j < m) sacc = sacc - a[i * MMAX + j] * x[j];
-      x[i] = sacc / a[i * MMAX + i];
+      x[i] = sacc * rdiag[i];
     }
   }
 }
@@ -172,7 +188,7 @@ __device__ __forceinline__ void lu_solve(const double* a, const int* piv, int m,
 template <int L, int ROWS, int MMAX>
 __device__ __forceinline__ void stage_solve(const double (&F)[ROWS], const double (&corr)[ROWS],
                                             double (&k)[ROWS], const double (&Q)[ROWS][MMAX], int Meff,
-                                            const double* LU, const int* piv) {
+                                            const double* LU, const double* rdiag, const int* piv) {
   double z[MMAX], y[MMAX];
 #pragma unroll
   for (int i2 = 0; i2 < MMAX; ++i2) {
@@ -185,7 +201,7 @@ __device__ __forceinline__ void stage_solve(const double (&F)[ROWS], const doubl
     }
     y[i2] = z[i2];
   }
-  if (Meff > 0) lu_solve<MMAX>(LU, piv, Meff, y);
+  if (Meff > 0) lu_solve<MMAX>(LU, rdiag, piv, Meff, y);
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     double qw = 0.0;
@@ -204,8 +220,9 @@ struct CellResult {
 // readings: clipped last step, err_n = 1 before the first acceptance and updated on
 // acceptance, basis reused after a rejection, non-finite u* or err rejected).
 template <int L, int ROWS, int MMAX, class RT>
-__device__ CellResult integrate_cell(const DevMech& m, const Launch& P, double (&u)[ROWS], double p,
-                                     const double (&s)[ROWS], const SegLds<RT>& S, int lane) {
+__device__ CellResult integrate_cell(const DevMech& m, const MechLds& tab, const Launch& P,
+                                     double (&u)[ROWS], double p, const double (&s)[ROWS],
+                                     const SegLds<RT>& S, int lane) {
   CellResult res{0, 0, 0};
   const int N = m.ns + 1;
   const double dt = P.dt;
@@ -233,8 +250,8 @@ __device__ CellResult integrate_cell(const DevMech& m, const Launch& P, double (
       last = true;
     }
     if (!basis_valid) {
-      rhs_forced<L, ROWS, RT, true>(m, u, p, s, fn, S, lane, &base, wbase);
-      Meff = arnoldi<L, ROWS, MMAX, RT>(m, P, u, fn, base, wbase, Q, S, lane);
+      rhs_forced<L, ROWS, RT, true>(m, tab, u, p, s, fn, S, lane, &base, wbase);
+      Meff = arnoldi<L, ROWS, MMAX, RT>(m, tab, P, u, fn, base, wbase, Q, S, lane);
       basis_valid = true;
     }
     // L = I - h gamma H, factored once per attempt.  Only the Hessenberg part of the
@@ -245,7 +262,7 @@ __device__ CellResult integrate_cell(const DevMech& m, const Launch& P, double (
         S.LU[i * MMAX + j] = (i == j ? 1.0 : 0.0) - h * G * hij;
       }
     lds_sync();
-    if (Meff > 0 && !lu_factor<MMAX>(S.LU, S.piv, Meff)) {
+    if (Meff > 0 && !lu_factor<MMAX>(S.LU, S.rdiag, S.piv, Meff)) {
       ++attempts;
       ++res.rejected;
       h *= 0.2;
@@ -260,34 +277,34 @@ __device__ CellResult integrate_cell(const DevMech& m, const Launch& P, double (
     // Stage 1: F1 = f_n.
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) corr[i] = 0.0;
-    stage_solve<L, ROWS, MMAX>(fn, corr, k1, Q, Meff, S.LU, S.piv);
+    stage_solve<L, ROWS, MMAX>(fn, corr, k1, Q, Meff, S.LU, S.rdiag, S.piv);
     // Stage 2: F2 = f(u + h a21 k1) + (g21/g) k1.
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A21 * k1[i]);
-    rhs_forced<L, ROWS, RT, false>(m, arg, p, s, fs, S, lane, nullptr, wtmp);
+    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
       corr[i] = (G21 / G) * k1[i];
       F[i] = fs[i] + corr[i];
     }
-    stage_solve<L, ROWS, MMAX>(F, corr, k2, Q, Meff, S.LU, S.piv);
+    stage_solve<L, ROWS, MMAX>(F, corr, k2, Q, Meff, S.LU, S.rdiag, S.piv);
     // Stage 3: F3 = f(u + h(a31 k1 + a32 k2)) + (g31 k1 + g32 k2)/g.
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A31 * k1[i] + A32 * k2[i]);
-    rhs_forced<L, ROWS, RT, false>(m, arg, p, s, fs, S, lane, nullptr, wtmp);
+    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
       corr[i] = (G31 * k1[i] + G32 * k2[i]) / G;
       F[i] = fs[i] + corr[i];
     }
-    stage_solve<L, ROWS, MMAX>(F, corr, k3, Q, Meff, S.LU, S.piv);
+    stage_solve<L, ROWS, MMAX>(F, corr, k3, Q, Meff, S.LU, S.rdiag, S.piv);
     // Stage 4 reuses f of stage 3 (a41 = a31, a42 = a32, a43 = 0).
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
       corr[i] = (G41 * k1[i] + G42 * k2[i] + G43 * k3[i]) / G;
       F[i] = fs[i] + corr[i];
     }
-    stage_solve<L, ROWS, MMAX>(F, corr, k4, Q, Meff, S.LU, S.piv);
+    stage_solve<L, ROWS, MMAX>(F, corr, k4, Q, Meff, S.LU, S.rdiag, S.piv);
 
     double us[ROWS];
 #pragma unroll

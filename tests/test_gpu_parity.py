@@ -10,8 +10,8 @@ Tolerances (derived from the arithmetic):
   result by a fraction of the tolerance scale atol + rtol |u| (measured by an
   FMA-contracted twin build of the oracle on the same cells: the "envelope").  The FP64
   GPU result must lie within 4x that envelope (plus 0.05) in the normalized error
-  |gpu - oracle| / (atol + rtol |oracle|), with a count-match rate no more than 0.1
-  below the twin's;
+  |gpu - oracle| / (atol + rtol |oracle|), with a count-match rate within three binomial
+  standard deviations (+0.02) of the twin's on the same sample;
 * mixed FP32/FP64: normalized error <= max(10, 4x envelope) against the FP64 oracle,
   i.e. 1e-5 relative (10 rtol) on species above atol/rtol.
 """
@@ -22,6 +22,11 @@ from gpu_util import dev_state, envelope, gpu_integrate, normalized, parity, par
 from paper_1712_00953_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+
+def match_floor(env_match, n):
+    """Lowest acceptable accept/reject count-match rate for an n-cell sample."""
+    return env_match - 3.0 * np.sqrt(max(env_match * (1 - env_match), 1e-4) / n) - 0.02
 
 A_SCALE = 1e-8
 MAX_ATT = 20000
@@ -127,13 +132,13 @@ def test_adaptive_parity_fp64(R, orc, cfg, n):
     _report(f"adaptive fp64 cfg{cfg}", d)
     assert np.all(g[4] == 0) and np.all(o[4] == 0)
     assert mx <= 4 * env["env_max"] + 0.05
-    assert d["match_frac"] >= env["env_match"] - 0.1
+    assert d["match_frac"] >= match_floor(env["env_match"], st.n_cells)
     m.close()
 
 
 def test_adaptive_parity_fp64_cfg4(R, orc):
     w = synth.workload(4, a_scale=A_SCALE)
-    idx = synth.stratified_sample(w.states.T, 128, 104)
+    idx = synth.stratified_sample(w.states.T, 256, 104)
     st = w.states.subset(idx)
     m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
     g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
@@ -143,7 +148,7 @@ def test_adaptive_parity_fp64_cfg4(R, orc):
     _report("adaptive fp64 cfg4", d)
     assert np.all(g[4] == 0)
     assert mx <= 4 * env["env_max"] + 0.05
-    assert d["match_frac"] >= env["env_match"] - 0.1
+    assert d["match_frac"] >= match_floor(env["env_match"], st.n_cells)
     m.close()
 
 
@@ -251,6 +256,6 @@ def test_full_batch_sampled(R, orc, cfg, n_check):
     d.update(sumY_drift=float(np.abs(g[0].sum(0) - st.Y.sum(0)).max()))
     _report(f"full cfg{cfg}", d)
     assert mx <= 4 * env["env_max"] + 0.05
-    assert d["match_frac"] >= env["env_match"] - 0.1
+    assert d["match_frac"] >= match_floor(env["env_match"], n_check)
     assert d["sumY_drift"] <= 1e-9
     m.close()
