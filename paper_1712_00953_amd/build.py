@@ -20,16 +20,20 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = [HIPCC, *FLAGS, "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
-           "-o", LIB + ".tmp", SRC]
+def build(verbose: bool = False, defines: dict | None = None, out: str | None = None) -> str:
+    """Compiles the library (to `out`, default the in-tree librok4e.so); `defines` sets
+    the tuning macros (ROK4E_OCC_ROWS1, ROK4E_RX_UNROLL)."""
+    lib = out or LIB
+    dflags = [f"-D{k}={v}" for k, v in (defines or {}).items()]
+    cmd = [HIPCC, *FLAGS, *dflags, "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
+           "-o", lib + ".tmp", SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

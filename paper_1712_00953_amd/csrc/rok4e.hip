@@ -22,8 +22,16 @@ __global__ void k_zero_u32(unsigned int* x) { *x = 0u; }
 // Persistent integrator: every segment of L lanes pulls cells from a device counter
 // until the batch is exhausted, so cells with 1 and 1000 attempts share the chip
 // without waiting on each other.
+// Waves per SIMD the register allocation is held to: three for one row slot per lane
+// (no spills), two for larger layouts.
+#ifndef ROK4E_OCC_ROWS1
+#define ROK4E_OCC_ROWS1 3
+#endif
+template <int ROWS>
+constexpr int occupancy() { return ROWS == 1 ? ROK4E_OCC_ROWS1 : 2; }
+
 template <int L, int ROWS, int MMAX, class RT>
-__global__ void __launch_bounds__(256, 2) k_integrate(DevMech m, Launch P) {
+__global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m, Launch P) {
   extern __shared__ __align__(16) char smem[];
   const MechLds t = load_mech_lds(m, smem);
   const int lane = (int)(threadIdx.x % L);
@@ -166,9 +174,8 @@ struct rok4e_mech {
   // host copy of the mechanism
   std::vector<double> W, cp, hf, par;          // par: 6 x nr
   std::vector<int> reac, prod;                 // 2 x nr
-  std::vector<std::vector<std::pair<int, int>>> lists;   // (j, nu) per species
   // device table image for the current layout
-  int image_lp = -1;
+  int image_key = -1;
   DevMech dm{};
   void* d_image = nullptr;
   unsigned int* d_queue = nullptr;
@@ -216,24 +223,22 @@ const Variant* pick_variant(int ns, const rok4e_options& o) {
   return best;
 }
 
-// Per-segment LDS: c, dc [LP] and the signed rates [2 NRP + 1], kf, kr [NRP] in the rate
-// type; H, LU [MMAX^2], 1/diag(U) [MMAX] in FP64; piv [MMAX].
+// Per-segment LDS: species arrays [3][LP] and kf, kr [NRP] in the rate type; H, LU
+// [MMAX^2], 1/diag(U) [MMAX] in FP64; piv [MMAX].
 struct SegLayout {
-  int bytes, off_dc, off_q, off_kf, off_kr, off_H, off_LU, off_rdiag, off_piv;
+  int bytes, off_kf, off_kr, off_H, off_LU, off_rdiag, off_piv;
 };
 
 int al16(int x) { return (x + 15) & ~15; }
 
+int rate_bytes(int prec) { return prec == ROK4E_FP64 ? 8 : 4; }
+
 SegLayout seg_layout(int nr, const Variant& v) {
-  const int rt = v.prec == ROK4E_FP64 ? 8 : 4;
+  const int rt = rate_bytes(v.prec);
   const int lp = v.L * v.rows;
   const int nrp = (std::max(nr, 1) + 1) & ~1;
   SegLayout s{};
-  int off = al16(lp * rt);
-  s.off_dc = off;
-  off = al16(off + lp * rt);
-  s.off_q = off;
-  off = al16(off + (2 * nrp + 1) * rt);
+  int off = al16(3 * lp * rt);
   s.off_kf = off;
   off = al16(off + nrp * rt);
   s.off_kr = off;
@@ -250,23 +255,18 @@ SegLayout seg_layout(int nr, const Variant& v) {
   return s;
 }
 
-// Builds (or reuses) the table image for the handle's current layout; see DevMech.
+// Builds (or reuses) the table image for the handle's current layout and rate type; see
+// DevMech.
 int ensure_image(rok4e_mech* m) {
   const int lp = m->var->L * m->var->rows;
-  if (m->image_lp == lp && m->d_image) return ROK4E_OK;
+  const int rb = rate_bytes(m->var->prec);
+  const int key = lp * 64 + rb;
+  if (m->image_key == key && m->d_image) return ROK4E_OK;
   const int ns = m->ns, nr = m->nr;
   const int nrp = (std::max(nr, 1) + 1) & ~1;
-  int D = 0;
-  for (const auto& l : m->lists) {
-    int len = 0;
-    for (const auto& e : l) len += std::abs(e.second);
-    D = std::max(D, len);
-  }
-  D = std::max(8, (D + 7) & ~7);
   const int off_spec = al16(6 * nrp * 8);
-  const int off_rx = al16(off_spec + 4 * lp * 8);
-  const int off_gidx = al16(off_rx + nrp * 4);
-  const int bytes = al16(off_gidx + D * lp * 4);
+  const int off_rxo = al16(off_spec + 4 * lp * 8);
+  const int bytes = al16(off_rxo + nrp * 8);
   std::vector<char> img(bytes, 0);
   double* par = (double*)img.data();
   for (int q = 0; q < 6; ++q)
@@ -279,28 +279,19 @@ int ensure_image(rok4e_mech* m) {
     sp[2 * lp + r] = spc ? m->cp[r] : 0.0;
     sp[3 * lp + r] = spc ? m->hf[r] : 0.0;
   }
-  int* rx = (int*)(img.data() + off_rx);
+  uint32_t* rxo = (uint32_t*)(img.data() + off_rxo);
+  auto off = [&](int k) { return (uint32_t)((k < 0 ? ns : k) * rb); };
   for (int j = 0; j < nr; ++j) {
-    int packed = 0;
-    const int sl[4] = {m->reac[2 * j], m->reac[2 * j + 1], m->prod[2 * j], m->prod[2 * j + 1]};
-    for (int a = 0; a < 4; ++a) packed |= (sl[a] < 0 ? ns : sl[a]) << (8 * a);
-    rx[j] = packed;
-  }
-  int* g = (int*)(img.data() + off_gidx);
-  for (int r = 0; r < lp; ++r) {
-    int d = 0;
-    if (r < ns)
-      for (const auto& e : m->lists[r])
-        for (int c = 0; c < std::abs(e.second); ++c) g[(d++) * lp + r] = e.second > 0 ? e.first : nrp + e.first;
-    for (; d < D; ++d) g[d * lp + r] = 2 * nrp;
+    rxo[2 * j] = off(m->reac[2 * j]) | off(m->reac[2 * j + 1]) << 16;
+    rxo[2 * j + 1] = off(m->prod[2 * j]) | off(m->prod[2 * j + 1]) << 16;
   }
   if (m->d_image) (void)hipFree(m->d_image);
   m->d_image = nullptr;
   hipError_t e = hipMalloc(&m->d_image, bytes);
   if (e == hipSuccess) e = hipMemcpy(m->d_image, img.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e);
-  m->dm = DevMech{ns, nr, nrp, lp, D, off_spec, off_rx, off_gidx, bytes, (const int4*)m->d_image};
-  m->image_lp = lp;
+  m->dm = DevMech{ns, nr, nrp, lp, off_spec, off_rxo, bytes, (const int4*)m->d_image};
+  m->image_key = key;
   return ROK4E_OK;
 }
 
@@ -376,8 +367,6 @@ Launch base_launch(rok4e_mech* m, int64_t n, double* Y, double* T, const double*
   P.rej = m->d_rej;
   P.status = m->d_status;
   P.seg_bytes = sl.bytes;
-  P.off_dc = sl.off_dc;
-  P.off_q = sl.off_q;
   P.off_kf = sl.off_kf;
   P.off_kr = sl.off_kr;
   P.off_H = sl.off_H;
@@ -470,25 +459,6 @@ int rok4e_mech_create(const rok4e_mech_desc* d, const rok4e_options* o, rok4e_me
   if (nr > 0) {
     m->reac.assign(d->reac, d->reac + 2 * nr);
     m->prod.assign(d->prod, d->prod + 2 * nr);
-  }
-  // Species-major production lists: for species k, (reaction j, net coefficient) for
-  // every reaction with a non-zero net coefficient, in increasing j.
-  m->lists.assign(ns, {});
-  for (int j = 0; j < nr; ++j) {
-    int sp[4], nu[4], nsp = 0;
-    auto add = [&](int r, int c) {
-      if (r < 0) return;
-      int i = 0;
-      while (i < nsp && sp[i] != r) ++i;
-      if (i == nsp) { sp[nsp] = r; nu[nsp] = 0; ++nsp; }
-      nu[i] += c;
-    };
-    add(d->reac[2 * j], -1);
-    add(d->reac[2 * j + 1], -1);
-    add(d->prod[2 * j], +1);
-    add(d->prod[2 * j + 1], +1);
-    for (int i = 0; i < nsp; ++i)
-      if (nu[i] != 0) m->lists[sp[i]].push_back({j, nu[i]});
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, m->device) != hipSuccess) {

@@ -3,15 +3,22 @@
 // Layout: one cell per "segment" of L lanes (L = 16, 32 or 64).  State row r of a cell
 // (species 0..ns-1, then T at row ns) lives in lane r % L, slot r / L of that segment
 // (ROWS slots per lane).  Reactions are taken round-robin by the segment's lanes for
-// the rate evaluation.  Concentrations and rates of progress are staged through a
-// per-segment LDS region; the small M x M projected matrices live there too.
+// the rate evaluation.  The segment's LDS scratch holds per species the concentration,
+// its increment and a production accumulator: the reaction lanes read the
+// concentrations and add their signed rates of progress into the accumulators with LDS
+// float atomics, so the production sums need no per-species gather.  The small M x M
+// projected matrices live in the segment's scratch too.
 //
-// Reductions over a segment follow one fixed tree (16-lane butterfly, then lane
-// halves, then slots pairwise), so results do not depend on L or ROWS.
+// Reductions over a segment follow one fixed tree (16-lane butterfly, then rows
+// pairwise, then slots pairwise).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#ifndef ROK4E_RX_UNROLL
+#define ROK4E_RX_UNROLL 1
+#endif
 
 namespace rok4e {
 
@@ -33,17 +40,16 @@ constexpr double E1 = BH1 - B1, E2 = BH2 - B2, E3 = BH3 - 0.0, E4 = 0.0 - B4;
 
 // Device view of a mechanism: one contiguous table image in global memory, copied to
 // LDS once per block by the kernels.  Image layout (NRP = reaction count rounded to even,
-// LP = lanes x slots of the layout, D = production-list length):
+// LP = lanes x slots of the layout):
 //   double par[6][NRP]   ln A_f, b_f, E_f, ln A_r, b_r, E_r
 //   double spec[4][LP]   W, 1/W, c_p, h_f per state row (zeros/ones past the species)
-//   int    rx[NRP]       species of reaction j packed in bytes (reac0, reac1, prod0,
-//                        prod1); an absent slot holds ns, whose concentration is 1
-//   int    gidx[D][LP]   production list of row r: indices into the signed rates
-//                        qs = (q_0..q_{NRP-1}, -q_0..-q_{NRP-1}, 0); a coefficient of
-//                        +-2 appears as two entries, padding points at the final 0
+//   uint2  rxo[NRP]      byte offsets (species x size of the rate type) of the species of
+//                        reaction j in the per-cell species arrays: .x = reac0 | reac1 << 16,
+//                        .y = prod0 | prod1 << 16; an absent slot holds the offset of
+//                        entry ns (concentration 1, increment 0)
 struct DevMech {
-  int ns, nr, nrp, lp, D;
-  int off_spec, off_rx, off_gidx, image_bytes;
+  int ns, nr, nrp, lp;
+  int off_spec, off_rxo, image_bytes;
   const int4* image;
 };
 
@@ -52,8 +58,7 @@ struct MechLds {
   const double* lnAf; const double* bf; const double* Ef;
   const double* lnAr; const double* br; const double* Er;
   const double* W; const double* invW; const double* cp; const double* hf;
-  const int* rx;
-  const int* gidx;
+  const uint2* rxo;
 };
 
 // Per-launch arguments of the integrator.
@@ -64,7 +69,7 @@ struct Launch {
   int M, max_attempts, fixed_steps;
   unsigned int* queue;
   int32_t* acc; int32_t* rej; int32_t* status;
-  int seg_bytes, off_dc, off_q, off_kf, off_kr, off_H, off_LU, off_rdiag, off_piv;
+  int seg_bytes, off_kf, off_kr, off_H, off_LU, off_rdiag, off_piv;
 };
 
 // Copies the table image to the start of the block's LDS and returns the view.  All
@@ -79,8 +84,7 @@ __device__ __forceinline__ MechLds load_mech_lds(const DevMech& m, char* lds) {
   t.lnAr = par + 3 * m.nrp; t.br = par + 4 * m.nrp; t.Er = par + 5 * m.nrp;
   const double* sp = (const double*)(lds + m.off_spec);
   t.W = sp; t.invW = sp + m.lp; t.cp = sp + 2 * m.lp; t.hf = sp + 3 * m.lp;
-  t.rx = (const int*)(lds + m.off_rx);
-  t.gidx = (const int*)(lds + m.off_gidx);
+  t.rxo = (const uint2*)(lds + m.off_rxo);
   return t;
 }
 
@@ -103,15 +107,17 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
 }
-// lane ^ 16 within each half of the wave
-__device__ __forceinline__ double swz16(double x) {
+// DPP move restricted to the rows in ROWMASK; the other rows receive +0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_rows(double x) {
   int lo = __double2loint(x), hi = __double2hiint(x);
-  lo = __builtin_amdgcn_ds_swizzle(lo, 0x401F);
-  hi = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xF, false);
   return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float swz16(float x) {
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F));
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_rows(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xF, false));
 }
 __device__ __forceinline__ double readlane(double x, int l) {
   int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
@@ -123,15 +129,27 @@ __device__ __forceinline__ float readlane(float x, int l) {
 }
 __device__ __forceinline__ int readlane(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
 
-// Sum over the L lanes of a segment; every lane receives the result.
+// Sum over the L lanes of a segment; every lane receives the result.  Within a row of 16
+// lanes a butterfly of DPP moves leaves the row sum in every lane; across rows the sums
+// are combined pairwise with row broadcasts ((r0 + r1) + (r2 + r3) for a full wave), all
+// on the vector ALU.  Additions are commutative bit for bit, so every lane, and every
+// layout, gets the same bits.
 template <int L, class V>
 __device__ __forceinline__ V seg_sum1(V x) {
   x = x + dpp<0xB1>(x);     // quad_perm [1,0,3,2]
   x = x + dpp<0x4E>(x);     // quad_perm [2,3,0,1]
   x = x + dpp<0x141>(x);    // row_half_mirror: pairs the two quads of each half-row
   x = x + dpp<0x140>(x);    // row_mirror: pairs the two half-rows of each row
-  if constexpr (L >= 32) x = x + swz16(x);
-  if constexpr (L == 64) x = readlane(x, 0) + readlane(x, 32);
+  if constexpr (L >= 32) {
+    x = x + dpp_rows<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3: r0 + r1, r2 + r3
+  }
+  if constexpr (L == 64) {
+    x = x + dpp_rows<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    x = readlane(x, 63);
+  } else if constexpr (L == 32) {
+    const V a = readlane(x, 31), b = readlane(x, 63);
+    x = (threadIdx.x & 32) ? b : a;
+  }
   return x;
 }
 
@@ -181,12 +199,14 @@ __device__ __forceinline__ bool finite_(V x) { return __builtin_isfinite(x); }
 
 // -------------------------------------------------------- right-hand side ----
 
-// Per-segment LDS scratch of the right-hand side.
+// Per-segment LDS scratch of the right-hand side.  spc holds three arrays of LP entries:
+// concentrations of the base state, their increments (difference evaluation) and the
+// production accumulators, so species k sits at spc[k], spc[LP + k], spc[2 LP + k]
+// (8-byte stride: consecutive species fall in different LDS banks).  Entry ns is the
+// absent reaction slot: concentration 1, increment 0, accumulator never read.
 template <class RT>
 struct RhsLds {
-  RT* c;    // [LP] concentrations of the base state; c[ns] = 1 (absent reaction slot)
-  RT* dc;   // [LP] their increments (difference evaluation); dc[ns] = 0
-  RT* qs;   // [2 NRP + 1] signed rates of progress (or increments), last entry 0
+  RT* spc;  // [3][LP]
   RT* kf;   // [NRP] forward rate constants of the base state
   RT* kr;   // [NRP] reverse rate constants of the base state
 };
@@ -204,6 +224,15 @@ __device__ __forceinline__ double expm1_small(double x) {
   return expm1(x);
 }
 
+// log1p for the small arguments of the difference evaluation (alternating series to x^5,
+// relative truncation error about x^5/6, below 2e-21 for |x| < 1e-4), the library routine
+// otherwise.
+__device__ __forceinline__ double log1p_small(double x) {
+  if (fabs(x) < 1e-4)
+    return x * (1.0 - x * (0.5 - x * (1.0 / 3.0 - x * (0.25 - x * 0.2))));
+  return log1p(x);
+}
+
 template <int L, int ROWS>
 __device__ __forceinline__ double row_value(const double (&u)[ROWS], int slot) {
   double v = 0.0;
@@ -213,15 +242,21 @@ __device__ __forceinline__ double row_value(const double (&u)[ROWS], int slot) {
   return v;
 }
 
-// Sum of the signed rates listed for state row r (fixed order: increasing reaction
-// index), i.e. sum_j nu_rj q_j.
+// LDS float atomic add (ds_add_f64 / ds_add_f32); the value is not returned.
 template <class RT>
-__device__ __forceinline__ RT production(const MechLds& t, const RT* qs, int D, int lp, int r) {
-  const int* g = t.gidx + r;
-  RT acc = 0;
-#pragma unroll 8
-  for (int d = 0; d < D; ++d) acc = acc + qs[g[d * lp]];
-  return acc;
+__device__ __forceinline__ void lds_add(RT* p, RT v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Adds -q to the accumulators of the reactants and +q to those of the products of one
+// reaction: a repeated species receives the term twice, a species on both sides -q and
+// +q.  An absent slot adds into the accumulator of entry ns, which is never read.
+template <int LP, class RT>
+__device__ __forceinline__ void scatter_rate(char* rb, uint2 o, RT q) {
+  lds_add((RT*)(rb + (o.x & 0xFFFFu)) + 2 * LP, -q);
+  lds_add((RT*)(rb + (o.x >> 16)) + 2 * LP, -q);
+  lds_add((RT*)(rb + (o.y & 0xFFFFu)) + 2 * LP, q);
+  lds_add((RT*)(rb + (o.y >> 16)) + 2 * LP, q);
 }
 
 // f(u) of one cell held by a segment (Sec. 4.4, e:cv_reactor, constant-pressure
@@ -234,7 +269,8 @@ template <int L, int ROWS, class RT, bool SAVE>
 __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const double (&u)[ROWS],
                                     double p, double (&f)[ROWS], const RhsLds<RT>& S, int lane,
                                     RhsBase* base, RT (&w)[ROWS]) {
-  const int ns = m.ns, nrp = m.nrp;
+  constexpr int LP = L * ROWS;
+  const int ns = m.ns;
   const int sT = ns / L, lT = ns % L;
   const double T = seg_bcast<L>(row_value<L, ROWS>(u, sT), lT);
 
@@ -252,11 +288,16 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    if (r < ns) S.c[r] = (RT)(1e-6 * rho * u[s] * t.invW[r]);
+    if (r < ns) {
+      S.spc[r] = (RT)(1e-6 * rho * u[s] * t.invW[r]);
+      S.spc[2 * LP + r] = (RT)0;
+    }
   }
   const double lnT = log(T);
   const double invRT = 1.0 / (kRu * T);
+  char* rb = (char*)S.spc;
   lds_sync();
+#pragma unroll ROK4E_RX_UNROLL
   for (int j = lane; j < m.nr; j += L) {
     const RT kf = arrhenius(t.lnAf[j], t.bf[j], t.Ef[j], lnT, invRT, RT(0));
     const RT kr = arrhenius(t.lnAr[j], t.br[j], t.Er[j], lnT, invRT, RT(0));
@@ -264,19 +305,17 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
       S.kf[j] = kf;
       S.kr[j] = kr;
     }
-    const int x = t.rx[j];
-    const RT pf = S.c[x & 0xFF] * S.c[(x >> 8) & 0xFF];
-    const RT pr = S.c[(x >> 16) & 0xFF] * S.c[(x >> 24) & 0xFF];
-    const RT q = kf * pf - kr * pr;
-    S.qs[j] = q;
-    S.qs[nrp + j] = -q;
+    const uint2 o = t.rxo[j];
+    const RT pf = *(const RT*)(rb + (o.x & 0xFFFFu)) * *(const RT*)(rb + (o.x >> 16));
+    const RT pr = *(const RT*)(rb + (o.y & 0xFFFFu)) * *(const RT*)(rb + (o.y >> 16));
+    scatter_rate<LP, RT>(rb, o, kf * pf - kr * pr);
   }
   lds_sync();
   double ph[ROWS];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const RT wk = (RT)1e6 * production<RT>(t, S.qs, m.D, m.lp, r);
+    const RT wk = r < ns ? (RT)1e6 * S.spc[2 * LP + r] : (RT)0;
     w[s] = wk;
     f[s] = (double)((RT)t.W[r] * wk * (RT)invrho);
     const RT hk = (RT)(t.hf[r] + t.cp[r] * (T - kTref));
@@ -291,17 +330,19 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
   lds_sync();   // the LDS scratch is reused by the next evaluation
 }
 
-// df = f(u + du) - f(u) in difference form, given the base evaluation at u (base, w,
-// S.c, S.kf, S.kr): every intermediate quantity is carried with its increment, formed
-// from increments only, so the result has the relative accuracy of the compute type
-// instead of the absolute accuracy eps |f| of a difference of two evaluations.
-// The increments of the scalar state functions (rho, ln T, 1/(Ru T)) are FP64.
+// df = f(u + du) - f(u) in difference form, given the base evaluation at u (base, w, the
+// concentrations in the records, S.kf, S.kr): every intermediate quantity is carried with
+// its increment, formed from increments only, so the result has the relative accuracy of
+// the compute type instead of the absolute accuracy eps |f| of a difference of two
+// evaluations.  The increments of the scalar state functions (rho, ln T, 1/(Ru T)) are
+// FP64.
 template <int L, int ROWS, class RT>
 __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, const RhsBase& B,
                                          const RT (&w)[ROWS], const double (&u)[ROWS],
                                          const double (&du)[ROWS], double (&df)[ROWS],
                                          const RhsLds<RT>& S, int lane) {
-  const int ns = m.ns, nrp = m.nrp;
+  constexpr int LP = L * ROWS;
+  const int ns = m.ns;
   const int sT = ns / L, lT = ns % L;
   const double T = B.T;
   const double dT = seg_bcast<L>(row_value<L, ROWS>(du, sT), lT);
@@ -323,32 +364,39 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    if (r < ns) S.dc[r] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * t.invW[r]);
+    if (r < ns) {
+      S.spc[LP + r] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * t.invW[r]);
+      S.spc[2 * LP + r] = (RT)0;
+    }
   }
-  const double dlnT = log1p(dT * B.invT);
+  const double dlnT = log1p_small(dT * B.invT);
   const double dinvRT = -dT / (kRu * T * T1);
+  char* rb = (char*)S.spc;
   lds_sync();
+#pragma unroll ROK4E_RX_UNROLL
   for (int j = lane; j < m.nr; j += L) {
     const RT kf = S.kf[j], kr = S.kr[j];
     const RT dkf = kf * (RT)expm1_small(t.bf[j] * dlnT - t.Ef[j] * dinvRT);
     const RT dkr = kr * (RT)expm1_small(t.br[j] * dlnT - t.Er[j] * dinvRT);
-    const int x = t.rx[j];
+    const uint2 o = t.rxo[j];
+    const RT* a0 = (const RT*)(rb + (o.x & 0xFFFFu));
+    const RT* a1 = (const RT*)(rb + (o.x >> 16));
+    const RT* b0 = (const RT*)(rb + (o.y & 0xFFFFu));
+    const RT* b1 = (const RT*)(rb + (o.y >> 16));
     // products of concentrations with increments: d(ab) = (a + da) db + da b
-    const int a0 = x & 0xFF, a1 = (x >> 8) & 0xFF, b0 = (x >> 16) & 0xFF, b1 = (x >> 24) & 0xFF;
-    const RT ca = S.c[a0], dca = S.dc[a0], cb = S.c[a1], dcb = S.dc[a1];
+    const RT ca = a0[0], dca = a0[LP], cb = a1[0], dcb = a1[LP];
     const RT pf = ca * cb, dpf = (ca + dca) * dcb + dca * cb;
-    const RT cc = S.c[b0], dcc = S.dc[b0], cd = S.c[b1], dcd = S.dc[b1];
+    const RT cc = b0[0], dcc = b0[LP], cd = b1[0], dcd = b1[LP];
     const RT pr = cc * cd, dpr = (cc + dcc) * dcd + dcc * cd;
     const RT dq = ((kf + dkf) * dpf + dkf * pf) - ((kr + dkr) * dpr + dkr * pr);
-    S.qs[j] = dq;
-    S.qs[nrp + j] = -dq;
+    scatter_rate<LP, RT>(rb, o, dq);
   }
   lds_sync();
   double ph[ROWS];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const double dw = 1e6 * (double)production<RT>(t, S.qs, m.D, m.lp, r), wk = (double)w[s];
+    const double dw = r < ns ? 1e6 * (double)S.spc[2 * LP + r] : 0.0, wk = (double)w[s];
     df[s] = t.W[r] * (dw * invrho1 - wk * drho * B.invrho * invrho1);
     const double hk = t.hf[r] + t.cp[r] * (T - kTref), dhk = t.cp[r] * dT;
     ph[s] = t.W[r] * ((hk + dhk) * dw + dhk * wk);

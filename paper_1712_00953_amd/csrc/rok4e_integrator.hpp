@@ -19,8 +19,7 @@ struct SegLds {
 template <class RT>
 __device__ __forceinline__ SegLds<RT> seg_lds(char* seg, const Launch& P) {
   SegLds<RT> S;
-  S.r = RhsLds<RT>{(RT*)seg, (RT*)(seg + P.off_dc), (RT*)(seg + P.off_q), (RT*)(seg + P.off_kf),
-                   (RT*)(seg + P.off_kr)};
+  S.r = RhsLds<RT>{(RT*)seg, (RT*)(seg + P.off_kf), (RT*)(seg + P.off_kr)};
   S.H = (double*)(seg + P.off_H);
   S.LU = (double*)(seg + P.off_LU);
   S.rdiag = (double*)(seg + P.off_rdiag);
@@ -28,13 +27,12 @@ __device__ __forceinline__ SegLds<RT> seg_lds(char* seg, const Launch& P) {
   return S;
 }
 
-// Constant entries of the segment's scratch: the concentration of an absent reaction
-// slot (1, increment 0) and the zero entry of the signed rates.
+// Constant entry of the segment's scratch: the absent reaction slot (concentration 1,
+// increment 0).
 template <class RT>
 __device__ __forceinline__ void init_seg(const DevMech& m, const SegLds<RT>& S) {
-  S.r.c[m.ns] = (RT)1;
-  S.r.dc[m.ns] = (RT)0;
-  S.r.qs[2 * m.nrp] = (RT)0;
+  S.r.spc[m.ns] = (RT)1;
+  S.r.spc[m.lp + m.ns] = (RT)0;
   lds_sync();
 }
 
@@ -189,16 +187,15 @@ template <int L, int ROWS, int MMAX>
 __device__ __forceinline__ void stage_solve(const double (&F)[ROWS], const double (&corr)[ROWS],
                                             double (&k)[ROWS], const double (&Q)[ROWS][MMAX], int Meff,
                                             const double* LU, const double* rdiag, const int* piv) {
+  // All MMAX projections are formed (columns past M_eff are zero), so the independent
+  // reductions interleave.
   double z[MMAX], y[MMAX];
 #pragma unroll
   for (int i2 = 0; i2 < MMAX; ++i2) {
-    z[i2] = 0.0;
-    if (i2 < Meff) {
-      double pr[ROWS];
+    double pr[ROWS];
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i) pr[i] = Q[i][i2] * F[i];
-      z[i2] = seg_sum<L, ROWS>(pr);
-    }
+    for (int i = 0; i < ROWS; ++i) pr[i] = Q[i][i2] * F[i];
+    z[i2] = seg_sum<L, ROWS>(pr);
     y[i2] = z[i2];
   }
   if (Meff > 0) lu_solve<MMAX>(LU, rdiag, piv, Meff, y);

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librok4e.so")
+# ROK4E_LIB names another build of the same library (e.g. one compiled with different
+# tuning macros); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("ROK4E_LIB") or os.path.join(HERE, "librok4e.so")
 
 OK, EINVAL, ENOMEM, EHIP, ECAPTURE, ENOTSUP = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1

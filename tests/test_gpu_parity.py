@@ -169,18 +169,26 @@ def test_mixed_parity(R, orc, cfg, n, rtol, tol):
     m.close()
 
 
-def test_layouts_are_bitwise_identical(R):
+def test_layouts_agree_and_runs_are_deterministic(R, orc):
+    """The block shape does not touch a cell's arithmetic, and a run repeats bit for bit
+    (the LDS accumulation order is fixed by the lane assignment); the lanes-per-cell
+    choice moves each species' production sum to another order, so every layout must sit
+    in the oracle's rounding envelope."""
     w = synth.workload(1, a_scale=A_SCALE, n_cells=300)
     st = w.states
-    outs = []
+    o, env = envelope(orc, w, st, w.dt, w.rtol, w.atol)
     for L in (16, 32, 64):
-        for wpb in (1, 4):
+        outs = []
+        for wpb in (1, 4, 4):
             m = R.Mech(w.mech, M=w.M, lanes_per_cell=L, waves_per_block=wpb)
             outs.append(gpu_integrate(m, st, w.dt, w.rtol, w.atol))
             m.close()
-    for o in outs[1:]:
-        for a, b in zip(outs[0], o):
-            np.testing.assert_array_equal(a, b)
+        for other in outs[1:]:
+            for a, b in zip(outs[0], other):
+                np.testing.assert_array_equal(a, b)
+        mx, p99 = normalized(outs[0], o, w.rtol, w.atol)
+        _report(f"layout L={L}", dict(norm_max=mx, norm_p99=p99, **env))
+        assert mx <= 4 * env["env_max"] + 0.05
 
 
 def test_edge_cases(R, orc):
