@@ -223,11 +223,13 @@ const Variant* pick_variant(int ns, const rok4e_options& o) {
   return best;
 }
 
-// Per-segment LDS: species arrays [3][LP] and kf, kr [NRP] in the rate type; H, LU
-// [MMAX^2], 1/diag(U) [MMAX] in FP64; piv [MMAX].
+// Per-segment LDS: species arrays [3][LP] and the rate-constant pairs [NRP] in the rate
+// type; H, LU [MMAX^2], 1/diag(U) [MMAX] in FP64; piv [MMAX].
 struct SegLayout {
-  int bytes, off_kf, off_kr, off_H, off_LU, off_rdiag, off_piv;
+  int bytes, off_k, off_H, off_LU, off_rdiag, off_piv;
 };
+
+int n_rx_padded(int nr) { return (std::max(nr, 1) + 1) & ~1; }
 
 int al16(int x) { return (x + 15) & ~15; }
 
@@ -236,13 +238,10 @@ int rate_bytes(int prec) { return prec == ROK4E_FP64 ? 8 : 4; }
 SegLayout seg_layout(int nr, const Variant& v) {
   const int rt = rate_bytes(v.prec);
   const int lp = v.L * v.rows;
-  const int nrp = (std::max(nr, 1) + 1) & ~1;
   SegLayout s{};
   int off = al16(3 * lp * rt);
-  s.off_kf = off;
-  off = al16(off + nrp * rt);
-  s.off_kr = off;
-  off = al16(off + nrp * rt);
+  s.off_k = off;
+  off = al16(off + n_rx_padded(nr) * 2 * rt);
   s.off_H = off;
   off = al16(off + v.mmax * v.mmax * 8);
   s.off_LU = off;
@@ -263,14 +262,20 @@ int ensure_image(rok4e_mech* m) {
   const int key = lp * 64 + rb;
   if (m->image_key == key && m->d_image) return ROK4E_OK;
   const int ns = m->ns, nr = m->nr;
-  const int nrp = (std::max(nr, 1) + 1) & ~1;
-  const int off_spec = al16(6 * nrp * 8);
+  const int nrp = n_rx_padded(nr);
+  const int off_spec = al16(3 * nrp * 16);
   const int off_rxo = al16(off_spec + 4 * lp * 8);
   const int bytes = al16(off_rxo + nrp * 8);
   std::vector<char> img(bytes, 0);
+  // (ln A_f, ln A_r), (b_f, E_f), (b_r, E_r); m->par holds ln A_f, b_f, E_f, ln A_r,
+  // b_r, E_r, each [nr]
   double* par = (double*)img.data();
-  for (int q = 0; q < 6; ++q)
-    for (int j = 0; j < nr; ++j) par[q * nrp + j] = m->par[q * nr + j];
+  const int pair_q[3][2] = {{0, 3}, {1, 2}, {4, 5}};
+  for (int a = 0; a < 3; ++a)
+    for (int j = 0; j < nr; ++j) {
+      par[(a * nrp + j) * 2] = m->par[pair_q[a][0] * nr + j];
+      par[(a * nrp + j) * 2 + 1] = m->par[pair_q[a][1] * nr + j];
+    }
   double* sp = (double*)(img.data() + off_spec);
   for (int r = 0; r < lp; ++r) {
     const bool spc = r < ns;
@@ -367,8 +372,7 @@ Launch base_launch(rok4e_mech* m, int64_t n, double* Y, double* T, const double*
   P.rej = m->d_rej;
   P.status = m->d_status;
   P.seg_bytes = sl.bytes;
-  P.off_kf = sl.off_kf;
-  P.off_kr = sl.off_kr;
+  P.off_k = sl.off_k;
   P.off_H = sl.off_H;
   P.off_LU = sl.off_LU;
   P.off_rdiag = sl.off_rdiag;

@@ -39,11 +39,15 @@ constexpr double BH1 = -0.217819895945721, BH2 = 1.03130847478467, BH3 = 0.18651
 constexpr double E1 = BH1 - B1, E2 = BH2 - B2, E3 = BH3 - 0.0, E4 = 0.0 - B4;
 
 // Device view of a mechanism: one contiguous table image in global memory, copied to
-// LDS once per block by the kernels.  Image layout (NRP = reaction count rounded to even,
-// LP = lanes x slots of the layout):
-//   double par[6][NRP]   ln A_f, b_f, E_f, ln A_r, b_r, E_r
-//   double spec[4][LP]   W, 1/W, c_p, h_f per state row (zeros/ones past the species)
-//   uint2  rxo[NRP]      byte offsets (species x size of the rate type) of the species of
+// LDS once per block by the kernels.  The Arrhenius parameters are stored as pairs that
+// one evaluation uses together, so each pair is one 16-byte LDS load and consecutive
+// reactions are contiguous (no bank conflicts).  Image layout (NRP = reaction count
+// rounded to even, LP = lanes x slots of the layout):
+//   double2 lnA[NRP]     (ln A_f, ln A_r)
+//   double2 bEf[NRP]     (b_f, E_f)
+//   double2 bEr[NRP]     (b_r, E_r)
+//   double  spec[4][LP]  W, 1/W, c_p, h_f per state row (zeros/ones past the species)
+//   uint2   rxo[NRP]     byte offsets (species x size of the rate type) of the species of
 //                        reaction j in the per-cell species arrays: .x = reac0 | reac1 << 16,
 //                        .y = prod0 | prod1 << 16; an absent slot holds the offset of
 //                        entry ns (concentration 1, increment 0)
@@ -55,11 +59,15 @@ struct DevMech {
 
 // LDS view of the table image.
 struct MechLds {
-  const double* lnAf; const double* bf; const double* Ef;
-  const double* lnAr; const double* br; const double* Er;
+  const double2* lnA; const double2* bEf; const double2* bEr;
   const double* W; const double* invW; const double* cp; const double* hf;
   const uint2* rxo;
 };
+
+// A pair of rate-type values (the forward and reverse rate constants of a reaction).
+template <class RT> struct Pair2;
+template <> struct Pair2<double> { using type = double2; };
+template <> struct Pair2<float> { using type = float2; };
 
 // Per-launch arguments of the integrator.
 struct Launch {
@@ -69,7 +77,7 @@ struct Launch {
   int M, max_attempts, fixed_steps;
   unsigned int* queue;
   int32_t* acc; int32_t* rej; int32_t* status;
-  int seg_bytes, off_kf, off_kr, off_H, off_LU, off_rdiag, off_piv;
+  int seg_bytes, off_k, off_H, off_LU, off_rdiag, off_piv;
 };
 
 // Copies the table image to the start of the block's LDS and returns the view.  All
@@ -78,10 +86,10 @@ __device__ __forceinline__ MechLds load_mech_lds(const DevMech& m, char* lds) {
   int4* dst = (int4*)lds;
   for (int i = threadIdx.x; i < m.image_bytes / 16; i += blockDim.x) dst[i] = m.image[i];
   __syncthreads();
-  const double* par = (const double*)lds;
   MechLds t;
-  t.lnAf = par; t.bf = par + m.nrp; t.Ef = par + 2 * m.nrp;
-  t.lnAr = par + 3 * m.nrp; t.br = par + 4 * m.nrp; t.Er = par + 5 * m.nrp;
+  t.lnA = (const double2*)lds;
+  t.bEf = t.lnA + m.nrp;
+  t.bEr = t.bEf + m.nrp;
   const double* sp = (const double*)(lds + m.off_spec);
   t.W = sp; t.invW = sp + m.lp; t.cp = sp + 2 * m.lp; t.hf = sp + 3 * m.lp;
   t.rxo = (const uint2*)(lds + m.off_rxo);
@@ -197,6 +205,16 @@ __device__ __forceinline__ float arrhenius(double lnA, double b, double E, doubl
 template <class V>
 __device__ __forceinline__ bool finite_(V x) { return __builtin_isfinite(x); }
 
+// 1/x for positive normal x: the hardware reciprocal refined by two Newton steps
+// (within about one ulp; used for cell-uniform quantities such as rho and T).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // -------------------------------------------------------- right-hand side ----
 
 // Per-segment LDS scratch of the right-hand side.  spc holds three arrays of LP entries:
@@ -206,30 +224,30 @@ __device__ __forceinline__ bool finite_(V x) { return __builtin_isfinite(x); }
 // absent reaction slot: concentration 1, increment 0, accumulator never read.
 template <class RT>
 struct RhsLds {
-  RT* spc;  // [3][LP]
-  RT* kf;   // [NRP] forward rate constants of the base state
-  RT* kr;   // [NRP] reverse rate constants of the base state
+  RT* spc;                        // [3][LP]
+  typename Pair2<RT>::type* k;    // [NRP] (k_f, k_r) of the base state
 };
 
 // Cell-uniform quantities of a base evaluation f(u), kept for the difference evaluation.
 struct RhsBase {
-  double T, invT, sigma, cpbar, rho, invrho, hsum;
+  double T, invT, invRT, sigma, cpbar, rho, invrho, invD, hsum;
 };
 
-// expm1 for the small arguments of the difference evaluation (Taylor series to x^5,
-// relative error below 2e-18 for |x| < 1e-3), the library routine otherwise.
+// expm1 for the small arguments of the difference evaluation: Taylor series to x^3
+// (relative truncation error about x^3/24, below 5e-17 for |x| < 1e-5), the library
+// routine otherwise.  The arguments are increments of ln k for a state perturbation of
+// relative size ~1e-8, so the series is the path taken.
 __device__ __forceinline__ double expm1_small(double x) {
-  if (fabs(x) < 1e-3)
-    return x * (1.0 + x * (0.5 + x * (1.0 / 6.0 + x * (1.0 / 24.0 + x * (1.0 / 120.0)))));
-  return expm1(x);
+  double s = x * (1.0 + x * (0.5 + x * (1.0 / 6.0)));
+  if (!(fabs(x) < 1e-5)) s = expm1(x);
+  return s;
 }
 
-// log1p for the small arguments of the difference evaluation (alternating series to x^5,
-// relative truncation error about x^5/6, below 2e-21 for |x| < 1e-4), the library routine
-// otherwise.
+// log1p for the small arguments of the difference evaluation: alternating series to x^4
+// (relative truncation error about x^4/5, below 3e-21 for |x| < 1e-5), the library
+// routine otherwise.
 __device__ __forceinline__ double log1p_small(double x) {
-  if (fabs(x) < 1e-4)
-    return x * (1.0 - x * (0.5 - x * (1.0 / 3.0 - x * (0.25 - x * 0.2))));
+  if (fabs(x) < 1e-5) return x * (1.0 - x * (0.5 - x * (1.0 / 3.0 - x * 0.25)));
   return log1p(x);
 }
 
@@ -283,8 +301,8 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
   }
   const double sigma = seg_sum<L, ROWS>(ps);
   const double cpbar = seg_sum<L, ROWS>(pc);
-  const double rho = p / (kRu * T * sigma);
-  const double invrho = 1.0 / rho;
+  const double rho = p * rcp(kRu * T * sigma);
+  const double invrho = rcp(rho);
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
@@ -294,17 +312,16 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
     }
   }
   const double lnT = log(T);
-  const double invRT = 1.0 / (kRu * T);
+  const double invT = rcp(T);
+  const double invRT = invT * (1.0 / kRu);
   char* rb = (char*)S.spc;
   lds_sync();
 #pragma unroll ROK4E_RX_UNROLL
   for (int j = lane; j < m.nr; j += L) {
-    const RT kf = arrhenius(t.lnAf[j], t.bf[j], t.Ef[j], lnT, invRT, RT(0));
-    const RT kr = arrhenius(t.lnAr[j], t.br[j], t.Er[j], lnT, invRT, RT(0));
-    if constexpr (SAVE) {
-      S.kf[j] = kf;
-      S.kr[j] = kr;
-    }
+    const double2 lnA = t.lnA[j], bEf = t.bEf[j], bEr = t.bEr[j];
+    const RT kf = arrhenius(lnA.x, bEf.x, bEf.y, lnT, invRT, RT(0));
+    const RT kr = arrhenius(lnA.y, bEr.x, bEr.y, lnT, invRT, RT(0));
+    if constexpr (SAVE) S.k[j] = {kf, kr};
     const uint2 o = t.rxo[j];
     const RT pf = *(const RT*)(rb + (o.x & 0xFFFFu)) * *(const RT*)(rb + (o.x >> 16));
     const RT pr = *(const RT*)(rb + (o.y & 0xFFFFu)) * *(const RT*)(rb + (o.y >> 16));
@@ -322,16 +339,17 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
     ph[s] = (double)(hk * (RT)t.W[r] * wk);
   }
   const double hsum = seg_sum<L, ROWS>(ph);
-  const double fT = -hsum / (rho * cpbar);
+  const double invD = rcp(rho * cpbar);
+  const double fT = -hsum * invD;
 #pragma unroll
   for (int s = 0; s < ROWS; ++s)
     if (s == sT && lane == lT) f[s] = fT;
-  if constexpr (SAVE) *base = RhsBase{T, 1.0 / T, sigma, cpbar, rho, invrho, hsum};
+  if constexpr (SAVE) *base = RhsBase{T, invT, invRT, sigma, cpbar, rho, invrho, invD, hsum};
   lds_sync();   // the LDS scratch is reused by the next evaluation
 }
 
-// df = f(u + du) - f(u) in difference form, given the base evaluation at u (base, w, the
-// concentrations in the records, S.kf, S.kr): every intermediate quantity is carried with
+// df = f(u + du) - f(u) in difference form, given the base evaluation at u (base, w, and
+// the concentrations and rate constants it left in LDS): every intermediate quantity is carried with
 // its increment, formed from increments only, so the result has the relative accuracy of
 // the compute type instead of the absolute accuracy eps |f| of a difference of two
 // evaluations.  The increments of the scalar state functions (rho, ln T, 1/(Ru T)) are
@@ -358,9 +376,10 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
   const double dcp = seg_sum<L, ROWS>(pc);
   const double sigma1 = B.sigma + dsigma, cp1 = B.cpbar + dcp;
   const double rho = B.rho;
-  const double drho = -rho * (dT * sigma1 + T * dsigma) / (T1 * sigma1);
+  const double invT1 = rcp(T1);
+  const double drho = -rho * (dT * sigma1 + T * dsigma) * (invT1 * rcp(sigma1));
   const double rho1 = rho + drho;
-  const double invrho1 = 1.0 / rho1;
+  const double invrho1 = rcp(rho1);
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
@@ -370,14 +389,16 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
     }
   }
   const double dlnT = log1p_small(dT * B.invT);
-  const double dinvRT = -dT / (kRu * T * T1);
+  const double dinvRT = -dT * (B.invRT * invT1);
   char* rb = (char*)S.spc;
   lds_sync();
 #pragma unroll ROK4E_RX_UNROLL
   for (int j = lane; j < m.nr; j += L) {
-    const RT kf = S.kf[j], kr = S.kr[j];
-    const RT dkf = kf * (RT)expm1_small(t.bf[j] * dlnT - t.Ef[j] * dinvRT);
-    const RT dkr = kr * (RT)expm1_small(t.br[j] * dlnT - t.Er[j] * dinvRT);
+    const double2 bEf = t.bEf[j], bEr = t.bEr[j];
+    const auto kj = S.k[j];
+    const RT kf = kj.x, kr = kj.y;
+    const RT dkf = kf * (RT)expm1_small(bEf.x * dlnT - bEf.y * dinvRT);
+    const RT dkr = kr * (RT)expm1_small(bEr.x * dlnT - bEr.y * dinvRT);
     const uint2 o = t.rxo[j];
     const RT* a0 = (const RT*)(rb + (o.x & 0xFFFFu));
     const RT* a1 = (const RT*)(rb + (o.x >> 16));
@@ -403,7 +424,8 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
   }
   const double dhsum = seg_sum<L, ROWS>(ph);
   const double D = rho * B.cpbar, dD = drho * cp1 + rho * dcp;
-  const double dfT = -(dhsum / (D + dD) - B.hsum * dD / (D * (D + dD)));
+  // f_T = -hsum / D: the increment is -(dhsum - hsum dD / D) / (D + dD)
+  const double dfT = -(dhsum - B.hsum * dD * B.invD) * rcp(D + dD);
 #pragma unroll
   for (int s = 0; s < ROWS; ++s)
     if (s == sT && lane == lT) df[s] = dfT;

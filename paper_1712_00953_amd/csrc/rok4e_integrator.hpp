@@ -19,7 +19,7 @@ struct SegLds {
 template <class RT>
 __device__ __forceinline__ SegLds<RT> seg_lds(char* seg, const Launch& P) {
   SegLds<RT> S;
-  S.r = RhsLds<RT>{(RT*)seg, (RT*)(seg + P.off_kf), (RT*)(seg + P.off_kr)};
+  S.r = RhsLds<RT>{(RT*)seg, (typename Pair2<RT>::type*)(seg + P.off_k)};
   S.H = (double*)(seg + P.off_H);
   S.LU = (double*)(seg + P.off_LU);
   S.rdiag = (double*)(seg + P.off_rdiag);
@@ -68,11 +68,13 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
   for (int i = 0; i < ROWS; ++i) sq[i] = fn[i] * fn[i];
   const double beta = sqrt(seg_sum<L, ROWS>(sq));
   if (beta == 0.0) return 0;
+  const double rbeta = 1.0 / beta;
 #pragma unroll
-  for (int i = 0; i < ROWS; ++i) Q[i][0] = fn[i] / beta;
+  for (int i = 0; i < ROWS; ++i) Q[i][0] = fn[i] * rbeta;
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) sq[i] = u[i] * u[i];
   const double delta = sqrt(P.eps_fd * (1.0 + sqrt(seg_sum<L, ROWS>(sq))));
+  const double rdelta = 1.0 / delta;
 #pragma unroll
   for (int j = 0; j < MMAX; ++j) {
     if (j >= Meff) break;
@@ -81,13 +83,8 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
     for (int i = 0; i < ROWS; ++i) du[i] = delta * Q[i][j];
     rhs_diff<L, ROWS, RT>(m, t, B, w, u, du, d, S.r, lane);
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i) wv[i] = d[i] / delta;
-    double wn0 = 0.0;
-    if (j + 1 < Meff) {
-#pragma unroll
-      for (int i = 0; i < ROWS; ++i) sq[i] = wv[i] * wv[i];
-      wn0 = sqrt(seg_sum<L, ROWS>(sq));
-    }
+    for (int i = 0; i < ROWS; ++i) wv[i] = d[i] * rdelta;
+    double hsq = 0.0;
 #pragma unroll
     for (int i2 = 0; i2 < MMAX; ++i2) {
       if (i2 > j) break;
@@ -96,20 +93,26 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
       for (int i = 0; i < ROWS; ++i) pr[i] = Q[i][i2] * wv[i];
       const double hij = seg_sum<L, ROWS>(pr);
       S.H[i2 * MMAX + j] = hij;
+      hsq = hsq + hij * hij;
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) wv[i] = wv[i] - hij * Q[i][i2];
     }
     if (j + 1 < Meff) {
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) sq[i] = wv[i] * wv[i];
-      const double hn = sqrt(seg_sum<L, ROWS>(sq));
+      const double hn2 = seg_sum<L, ROWS>(sq);
+      const double hn = sqrt(hn2);
+      // |J q_j| before the orthogonalization, from the orthogonal decomposition
+      // |w|^2 = sum_i h_ij^2 + h_{j+1,j}^2 (no separate reduction)
+      const double wn0 = sqrt(hsq + hn2);
       if (!(hn > 1e-12 * wn0)) {
         Meff = j + 1;
         break;
       }
       S.H[(j + 1) * MMAX + j] = hn;
+      const double rhn = 1.0 / hn;
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i) Q[i][j + 1] = wv[i] / hn;
+      for (int i = 0; i < ROWS; ++i) Q[i][j + 1] = wv[i] * rhn;
     }
   }
   lds_sync();
@@ -232,7 +235,8 @@ __device__ CellResult integrate_cell(const DevMech& m, const MechLds& tab, const
   RhsBase base;
   int Meff = 0;
   bool basis_valid = false;
-  double t = 0.0, h = P.h0 > 0.0 ? P.h0 : dt, err_prev = 1.0;
+  // ln of the last accepted error (err_prev = 1 before the first acceptance)
+  double t = 0.0, h = P.h0 > 0.0 ? P.h0 : dt, lerr_prev = 0.0;
   if (fixed) h = dt / P.fixed_steps;
   int attempts = 0, steps_done = 0;
 
@@ -291,14 +295,14 @@ __device__ CellResult integrate_cell(const DevMech& m, const MechLds& tab, const
     rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
-      corr[i] = (G31 * k1[i] + G32 * k2[i]) / G;
+      corr[i] = (G31 * k1[i] + G32 * k2[i]) * (1.0 / G);
       F[i] = fs[i] + corr[i];
     }
     stage_solve<L, ROWS, MMAX>(F, corr, k3, Q, Meff, S.LU, S.rdiag, S.piv);
     // Stage 4 reuses f of stage 3 (a41 = a31, a42 = a32, a43 = 0).
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
-      corr[i] = (G41 * k1[i] + G42 * k2[i] + G43 * k3[i]) / G;
+      corr[i] = (G41 * k1[i] + G42 * k2[i] + G43 * k3[i]) * (1.0 / G);
       F[i] = fs[i] + corr[i];
     }
     stage_solve<L, ROWS, MMAX>(F, corr, k4, Q, Meff, S.LU, S.rdiag, S.piv);
@@ -325,23 +329,24 @@ __device__ CellResult integrate_cell(const DevMech& m, const MechLds& tab, const
       if (r < N) {
         const double e = h * (E1 * k1[i] + E2 * k2[i] + E3 * k3[i] + E4 * k4[i]);
         const double sc = P.atol + P.rtol * fabs(us[i]);
-        const double ratio = e / sc;
+        const double ratio = e * rcp(sc);
         ss[i] = ratio * ratio;
         nb[i] = finite_(us[i]) ? 0.0 : 1.0;
       }
     }
-    double err = sqrt(seg_sum<L, ROWS>(ss) / N);
+    double err = sqrt(seg_sum<L, ROWS>(ss) * (1.0 / N));
     const double nbad = seg_sum<L, ROWS>(nb);
     if (!finite_(err) || nbad != 0.0) err = __builtin_huge_val();
-    // PI controller, alpha = 0.7/4, beta = 0.4/4.
-    const double fac = fmin(5.0, fmax(0.2, 0.8 * pow(fmax(err_prev, 1e-10), 0.1) /
-                                               pow(fmax(err, 1e-10), 0.175)));
+    // PI controller, alpha = 0.7/4, beta = 0.4/4:
+    // 0.8 err_prev^0.1 / err^0.175 = 0.8 exp(0.1 ln err_prev - 0.175 ln err).
+    const double lerr = log(fmax(err, 1e-10));
+    const double fac = fmin(5.0, fmax(0.2, 0.8 * exp(0.1 * lerr_prev - 0.175 * lerr)));
     const double hstar = h * fac;
     if (err <= 1.0) {
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) u[i] = us[i];
       t = last ? dt : t + h;
-      err_prev = err;
+      lerr_prev = lerr;
       h = hstar;
       ++res.accepted;
       basis_valid = false;
