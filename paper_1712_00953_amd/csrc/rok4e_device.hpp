@@ -174,6 +174,101 @@ __device__ __forceinline__ V seg_sum(const V (&x)[ROWS]) {
   }
 }
 
+// x + (x of lane i ^ 16) and x + (x of lane i ^ 32) in every lane, from the gfx950
+// row-swap permutes (v_permlane16_swap / v_permlane32_swap of x with itself leave the two
+// partners' values in two registers; their sum has the same bits in both lanes).
+__device__ __forceinline__ double add_xor16(double x) {
+  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ __forceinline__ float add_xor16(float x) {
+  const auto v = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(v[0]) + __uint_as_float(v[1]);
+}
+__device__ __forceinline__ double add_xor32(double x) {
+  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ __forceinline__ float add_xor32(float x) {
+  const auto v = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(v[0]) + __uint_as_float(v[1]);
+}
+
+// Sums over the L lanes of a segment of K values at once (K = 2, 4 or 8); every lane
+// receives all K sums in x.  On the first log2(min(K, 4)) butterfly levels (lane ^ 1,
+// lane ^ 2) the values are split between partner lanes: of every pair of values a lane
+// keeps one, chosen by its lane-index bit, and sends the other, so a level costs half the
+// moves and adds of K separate reductions.  The kept values are then summed over the
+// lanes with the same two low index bits: within a row by rotations by 4 and 8, across
+// rows by the lane ^ 16 and lane ^ 32 swaps.  Sum i is read from one fixed lane of the
+// segment (the rotation sums differ by lane in summation order, so the result is taken
+// from the same lane every time).
+template <int L, int K, class V>
+__device__ __forceinline__ void seg_sum_k(V (&x)[K]) {
+  static_assert(K == 2 || K == 4 || K == 8, "K must be 2, 4 or 8");
+  const int lid = (int)(threadIdx.x & 63);
+  const bool b0 = lid & 1, b1 = lid & 2;
+  constexpr int K1 = K / 2;
+  V y[K1];
+#pragma unroll
+  for (int m = 0; m < K1; ++m) {
+    const V keep = b0 ? x[2 * m + 1] : x[2 * m], send = b0 ? x[2 * m] : x[2 * m + 1];
+    y[m] = keep + dpp<0xB1>(send);            // quad_perm [1,0,3,2]: lane ^ 1
+  }
+  constexpr int K2 = K1 > 1 ? K1 / 2 : 1;
+  V z[K2];
+  if constexpr (K1 > 1) {
+#pragma unroll
+    for (int n = 0; n < K2; ++n) {
+      const V keep = b1 ? y[2 * n + 1] : y[2 * n], send = b1 ? y[2 * n] : y[2 * n + 1];
+      z[n] = keep + dpp<0x4E>(send);          // quad_perm [2,3,0,1]: lane ^ 2
+    }
+  } else {
+    z[0] = y[0] + dpp<0x4E>(y[0]);
+  }
+#pragma unroll
+  for (int n = 0; n < K2; ++n) {
+    V v = z[n];
+    v = v + dpp<0x124>(v);                     // row_ror:4
+    v = v + dpp<0x128>(v);                     // row_ror:8
+    if constexpr (L >= 32) v = add_xor16(v);
+    if constexpr (L == 64) v = add_xor32(v);
+    z[n] = v;
+  }
+  // Sum i sits in the lanes whose two low index bits are (i & 3) for K >= 4, (i & 1)
+  // with K = 2; it is read from the first such lane of the segment.
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int n = K >= 4 ? i >> 2 : 0;
+    const int q = K >= 4 ? (i & 3) : (i & 1);
+    if constexpr (L == 64) {
+      x[i] = readlane(z[n], q);
+    } else if constexpr (L == 32) {
+      const V a = readlane(z[n], q), c = readlane(z[n], 32 + q);
+      x[i] = (lid & 32) ? c : a;
+    } else {
+      x[i] = __shfl(z[n], (lid & ~15) + q, 64);
+    }
+  }
+}
+
+// seg_sum_k over the ROWS slots of each of K values (slots added first).
+template <int L, int ROWS, int K, class V>
+__device__ __forceinline__ void seg_sum_rows_k(const V (&x)[ROWS][K], V (&out)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    V a = x[0][k];
+#pragma unroll
+    for (int s = 1; s < ROWS; ++s) a = a + x[s][k];
+    out[k] = a;
+  }
+  seg_sum_k<L, K>(out);
+}
+
 // Value of x in lane `src` of this segment.
 template <int L, class V>
 __device__ __forceinline__ V seg_bcast(V x, int src) {
@@ -292,15 +387,15 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
   const int sT = ns / L, lT = ns % L;
   const double T = seg_bcast<L>(row_value<L, ROWS>(u, sT), lT);
 
-  double ps[ROWS], pc[ROWS];
+  double sc2[ROWS][2], sums[2];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;          // rows past the species have invW = cp = 0
-    ps[s] = (r < ns ? u[s] : 0.0) * t.invW[r];
-    pc[s] = (r < ns ? u[s] : 0.0) * t.cp[r];
+    sc2[s][0] = (r < ns ? u[s] : 0.0) * t.invW[r];
+    sc2[s][1] = (r < ns ? u[s] : 0.0) * t.cp[r];
   }
-  const double sigma = seg_sum<L, ROWS>(ps);
-  const double cpbar = seg_sum<L, ROWS>(pc);
+  seg_sum_rows_k<L, ROWS, 2>(sc2, sums);
+  const double sigma = sums[0], cpbar = sums[1];
   const double rho = p * rcp(kRu * T * sigma);
   const double invrho = rcp(rho);
 #pragma unroll
@@ -365,15 +460,15 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
   const double T = B.T;
   const double dT = seg_bcast<L>(row_value<L, ROWS>(du, sT), lT);
   const double T1 = T + dT;
-  double ps[ROWS], pc[ROWS];
+  double sc2[ROWS][2], sums[2];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    ps[s] = (r < ns ? du[s] : 0.0) * t.invW[r];
-    pc[s] = (r < ns ? du[s] : 0.0) * t.cp[r];
+    sc2[s][0] = (r < ns ? du[s] : 0.0) * t.invW[r];
+    sc2[s][1] = (r < ns ? du[s] : 0.0) * t.cp[r];
   }
-  const double dsigma = seg_sum<L, ROWS>(ps);
-  const double dcp = seg_sum<L, ROWS>(pc);
+  seg_sum_rows_k<L, ROWS, 2>(sc2, sums);
+  const double dsigma = sums[0], dcp = sums[1];
   const double sigma1 = B.sigma + dsigma, cp1 = B.cpbar + dcp;
   const double rho = B.rho;
   const double invT1 = rcp(T1);

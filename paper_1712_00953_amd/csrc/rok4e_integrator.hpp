@@ -190,16 +190,24 @@ template <int L, int ROWS, int MMAX>
 __device__ __forceinline__ void stage_solve(const double (&F)[ROWS], const double (&corr)[ROWS],
                                             double (&k)[ROWS], const double (&Q)[ROWS][MMAX], int Meff,
                                             const double* LU, const double* rdiag, const int* piv) {
-  // All MMAX projections are formed (columns past M_eff are zero), so the independent
-  // reductions interleave.
+  // All MMAX projections are formed (columns past M_eff are zero) and reduced together,
+  // in groups of up to eight.
   double z[MMAX], y[MMAX];
+  constexpr int KG = MMAX % 8 == 0 ? 8 : 4;
+  static_assert(MMAX % KG == 0, "MMAX must be a multiple of 4");
 #pragma unroll
-  for (int i2 = 0; i2 < MMAX; ++i2) {
-    double pr[ROWS];
+  for (int g = 0; g < MMAX; g += KG) {
+    double pr[ROWS][KG], zg[KG];
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i) pr[i] = Q[i][i2] * F[i];
-    z[i2] = seg_sum<L, ROWS>(pr);
-    y[i2] = z[i2];
+    for (int i = 0; i < ROWS; ++i)
+#pragma unroll
+      for (int k = 0; k < KG; ++k) pr[i][k] = Q[i][g + k] * F[i];
+    seg_sum_rows_k<L, ROWS, KG>(pr, zg);
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      z[g + k] = zg[k];
+      y[g + k] = zg[k];
+    }
   }
   if (Meff > 0) lu_solve<MMAX>(LU, rdiag, piv, Meff, y);
 #pragma unroll
@@ -334,8 +342,15 @@ __device__ CellResult integrate_cell(const DevMech& m, const MechLds& tab, const
         nb[i] = finite_(us[i]) ? 0.0 : 1.0;
       }
     }
-    double err = sqrt(seg_sum<L, ROWS>(ss) * (1.0 / N));
-    const double nbad = seg_sum<L, ROWS>(nb);
+    double en[ROWS][2], sums[2];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      en[i][0] = ss[i];
+      en[i][1] = nb[i];
+    }
+    seg_sum_rows_k<L, ROWS, 2>(en, sums);
+    double err = sqrt(sums[0] * (1.0 / N));
+    const double nbad = sums[1];
     if (!finite_(err) || nbad != 0.0) err = __builtin_huge_val();
     // PI controller, alpha = 0.7/4, beta = 0.4/4:
     // 0.8 err_prev^0.1 / err^0.175 = 0.8 exp(0.1 ln err_prev - 0.175 ln err).
