@@ -36,7 +36,7 @@ extern "C" {
 #define ROK4E_EINVAL (-1)    /* invalid argument (null pointer with n_cells > 0, sizes, tolerances, M) */
 #define ROK4E_ENOMEM (-2)    /* device allocation failed */
 #define ROK4E_EHIP (-3)      /* HIP runtime or launch error */
-#define ROK4E_ECAPTURE (-4)  /* workspace too small while the stream is being captured */
+#define ROK4E_ECAPTURE (-4)  /* workspace too small, or PER_ATTEMPT, while the stream is being captured */
 #define ROK4E_ENOTSUP (-5)   /* no kernel variant for this (n_species, M, precision, layout) */
 
 /* Per-cell status codes. */
@@ -51,9 +51,14 @@ extern "C" {
 #define ROK4E_FP64 0
 #define ROK4E_MIXED 1
 
-/* Cell scheduling. */
-#define ROK4E_PERSISTENT 0   /* one launch; waves pull cells from a device work queue */
-#define ROK4E_PER_ATTEMPT 1  /* one launch per attempt over the still-active cells */
+/* Cell scheduling (bitwise identical results).  PERSISTENT: one launch; segments pull
+ * cells from a device work queue and integrate each to dt.  PER_ATTEMPT: one launch per
+ * attempt over the cells still active, the per-cell integrator state (t, h, controller
+ * memory, counters, f(u_n) and the Krylov basis) carried in device memory between
+ * launches; the call synchronises the stream once per launch and returns
+ * ROK4E_ECAPTURE inside a stream capture.  A reference schedule for comparison. */
+#define ROK4E_PERSISTENT 0
+#define ROK4E_PER_ATTEMPT 1
 
 typedef struct rok4e_mech rok4e_mech;   /* opaque handle */
 
@@ -79,10 +84,12 @@ typedef struct {
   int32_t precision;      /* ROK4E_FP64 or ROK4E_MIXED */
   int32_t max_attempts;   /* attempts allowed per cell; <= 0 means 1000000 */
   int32_t fixed_steps;    /* 0: adaptive; n > 0: n equal steps, no error control */
-  int32_t lanes_per_cell; /* 0: automatic; else 16, 32 or 64 (result-neutral) */
-  int32_t waves_per_block;/* 0: automatic; 1..4 waves of 64 lanes (result-neutral) */
-  int32_t blocks_per_cu;  /* 0: automatic; persistent-grid blocks per compute unit */
-  int32_t scheduling;     /* ROK4E_PERSISTENT or ROK4E_PER_ATTEMPT (result-neutral) */
+  int32_t lanes_per_cell; /* 0: automatic; else 16, 32 or 64.  Changes the order in which
+                             the production sums accumulate: results agree to rounding */
+  int32_t waves_per_block;/* 0: automatic; 1..4 waves of 64 lanes (bitwise neutral) */
+  int32_t blocks_per_cu;  /* 0: automatic; persistent-grid blocks per compute unit
+                             (bitwise neutral) */
+  int32_t scheduling;     /* ROK4E_PERSISTENT or ROK4E_PER_ATTEMPT (bitwise neutral) */
   double h0;              /* first trial step; <= 0 means dt */
 } rok4e_options;
 

@@ -45,15 +45,97 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m,
     const int cell = seg_bcast<L>((int)ticket, 0);
     if (cell < 0 || (int64_t)cell >= P.n_cells) break;
     double u[ROWS], s[ROWS], p;
-    CellResult r{3, 0, 0};
+    CellState c{};
+    c.status = 3;
     if (load_cell<L, ROWS>(m, P, cell, lane, u, s, p)) {
-      r = integrate_cell<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane);
+      c = integrate_cell<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane);
       store_cell<L, ROWS>(m, P, cell, lane, u);
     }
     // every lane of the segment stores the same (segment-uniform) values
-    P.acc[cell] = r.accepted;
-    P.rej[cell] = r.rejected;
-    P.status[cell] = r.status;
+    P.acc[cell] = c.accepted;
+    P.rej[cell] = c.rejected;
+    P.status[cell] = c.status;
+  }
+}
+
+// Device buffers of the per-attempt schedule: the state each active cell carries from
+// one launch to the next (cell-major, so a segment's lanes read contiguous rows).
+struct AttemptWork {
+  CellState* st;          // [n]
+  double* fnq;            // [n][1 + MMAX][LP]: f(u_n) and the Krylov basis
+  double* H;              // [n][MMAX * MMAX]
+  const int32_t* act_in;  // cells active before this launch (unused on the first launch)
+  const unsigned int* n_in;
+  int32_t* act_out;       // cells still active after it
+  unsigned int* n_out;
+  int first;              // 1: every cell, starting from its initial state
+};
+
+// Per-attempt schedule: each launch performs one attempt of every active cell (the same
+// cell_attempt as the persistent kernel, so the results are bitwise identical) and
+// appends the cells that need another attempt to act_out.  The host relaunches until no
+// cell is active.
+template <int L, int ROWS, int MMAX, class RT>
+__global__ void __launch_bounds__(256, occupancy<ROWS>()) k_attempt(DevMech m, Launch P, AttemptWork W) {
+  extern __shared__ __align__(16) char smem[];
+  const MechLds t = load_mech_lds(m, smem);
+  const int lane = (int)(threadIdx.x % L);
+  char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
+  const SegLds<RT> S = seg_lds<RT>(seg, P);
+  init_seg<RT>(m, S);
+  constexpr int LP = L * ROWS;
+  const int64_t nact = W.first ? P.n_cells : (int64_t)*W.n_in;
+  const int64_t nseg = (int64_t)gridDim.x * (blockDim.x / L);
+  for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x / L) + threadIdx.x / L; idx < nact; idx += nseg) {
+    const int64_t cell = W.first ? idx : (int64_t)W.act_in[idx];
+    double u[ROWS], s[ROWS], p, fn[ROWS], Q[ROWS][MMAX];
+    const bool valid = load_cell<L, ROWS>(m, P, cell, lane, u, s, p);
+    double* fq = W.fnq + cell * (int64_t)((1 + MMAX) * LP);
+    double* Hc = W.H + cell * (int64_t)(MMAX * MMAX);
+    CellState c{};
+    bool run = false;
+    if (W.first) {
+      c.status = 3;
+      if (valid) {
+        cell_start(P, c);
+        run = cell_running(P, c);
+      }
+    } else {
+      c = W.st[cell];
+      run = true;
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        fn[i] = fq[i * L + lane];
+#pragma unroll
+        for (int j = 0; j < MMAX; ++j) Q[i][j] = fq[(1 + j) * LP + i * L + lane];
+      }
+      for (int i = lane; i < MMAX * MMAX; i += L) S.H[i] = Hc[i];
+      lds_sync();
+    }
+    if (run) {
+      cell_attempt<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane, c, fn, Q);
+      store_cell<L, ROWS>(m, P, cell, lane, u);
+      run = cell_running(P, c);
+    }
+    if (run) {
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        fq[i * L + lane] = fn[i];
+#pragma unroll
+        for (int j = 0; j < MMAX; ++j) fq[(1 + j) * LP + i * L + lane] = Q[i][j];
+      }
+      for (int i = lane; i < MMAX * MMAX; i += L) Hc[i] = S.H[i];
+      // every lane writes the same state; the segment's first lane appends the cell
+      W.st[cell] = c;
+      const unsigned int slot = atomicAdd(W.n_out, lane == 0 ? 1u : 0u);
+      const int pos = seg_bcast<L>((int)slot, 0);
+      W.act_out[pos] = (int32_t)cell;
+    } else {
+      P.acc[cell] = c.accepted;
+      P.rej[cell] = c.rejected;
+      P.status[cell] = c.status;
+    }
+    lds_sync();
   }
 }
 
@@ -130,18 +212,21 @@ __global__ void __launch_bounds__(256, 2) k_arnoldi(DevMech m, Launch P, double*
 // ------------------------------------------------------------ variant table ----
 
 using IntegrateFn = void (*)(DevMech, Launch);
+using AttemptFn = void (*)(DevMech, Launch, AttemptWork);
 using RhsFn = void (*)(DevMech, Launch, double*, double*);
 using ArnoldiFn = void (*)(DevMech, Launch, double*, double*, int32_t*);
 
 struct Variant {
   int L, rows, mmax, prec;
   IntegrateFn integrate;
+  AttemptFn attempt;
   ArnoldiFn arnoldi;
   RhsFn rhs;
 };
 
-#define ROK4E_VARIANT(Lv, Rv, Mv, T, P) \
-  Variant{Lv, Rv, Mv, P, k_integrate<Lv, Rv, Mv, T>, k_arnoldi<Lv, Rv, Mv, T>, k_rhs<Lv, Rv, T>}
+#define ROK4E_VARIANT(Lv, Rv, Mv, T, P)                                                       \
+  Variant{Lv, Rv, Mv, P, k_integrate<Lv, Rv, Mv, T>, k_attempt<Lv, Rv, Mv, T>, k_arnoldi<Lv, Rv, Mv, T>, \
+          k_rhs<Lv, Rv, T>}
 
 static const Variant kVariants[] = {
     ROK4E_VARIANT(16, 1, 4, double, ROK4E_FP64),  ROK4E_VARIANT(16, 1, 8, double, ROK4E_FP64),
@@ -185,6 +270,15 @@ struct rok4e_mech {
   int32_t* d_rej = nullptr;
   int32_t* d_status = nullptr;
   int64_t last_n = 0;
+  // per-attempt schedule: carried cell state, active lists and their counters
+  int64_t att_cap = 0;
+  const Variant* att_var = nullptr;   // layout the buffers are sized for
+  CellState* d_st = nullptr;
+  double* d_fnq = nullptr;
+  double* d_H = nullptr;
+  int32_t* d_act[2] = {nullptr, nullptr};
+  unsigned int* d_cnt = nullptr;   // [2]
+  unsigned int* h_cnt = nullptr;   // pinned host copy of one counter
 };
 
 namespace {
@@ -337,6 +431,31 @@ int shape_for(const rok4e_mech* m, const SegLayout& sl, int64_t n_cells, const v
   return ROK4E_OK;
 }
 
+// Buffers of the per-attempt schedule for n cells of the current layout.
+int ensure_attempt_work(rok4e_mech* m, int64_t n) {
+  const size_t per_cell = (size_t)(1 + m->var->mmax) * m->var->L * m->var->rows;
+  if (n <= m->att_cap && m->att_var == m->var) return ROK4E_OK;
+  void* bufs[] = {m->d_st, m->d_fnq, m->d_H, m->d_act[0], m->d_act[1]};
+  for (void* b : bufs) (void)hipFree(b);
+  m->d_st = nullptr;
+  m->d_fnq = m->d_H = nullptr;
+  m->d_act[0] = m->d_act[1] = nullptr;
+  m->att_cap = 0;
+  const int64_t cap = std::max(n, m->cap);
+  const size_t mm = (size_t)m->var->mmax * m->var->mmax;
+  hipError_t e = hipMalloc((void**)&m->d_st, cap * sizeof(CellState));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_fnq, cap * per_cell * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_H, cap * mm * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_act[0], cap * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_act[1], cap * sizeof(int32_t));
+  if (e == hipSuccess && !m->d_cnt) e = hipMalloc((void**)&m->d_cnt, 2 * sizeof(unsigned int));
+  if (e == hipSuccess && !m->h_cnt) e = hipHostMalloc((void**)&m->h_cnt, sizeof(unsigned int));
+  if (e != hipSuccess) return hip_fail(e);
+  m->att_cap = cap;
+  m->att_var = m->var;
+  return ROK4E_OK;
+}
+
 int ensure_workspace(rok4e_mech* m, int64_t n, hipStream_t stream) {
   if (n <= m->cap) return ROK4E_OK;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -380,6 +499,36 @@ Launch base_launch(rok4e_mech* m, int64_t n, double* Y, double* T, const double*
   return P;
 }
 
+// Per-attempt schedule: launch one attempt of every active cell, read back how many
+// remain, repeat (the stream is synchronised once per launch; not capturable).
+int run_per_attempt(rok4e_mech* m, const Launch& P, const SegLayout& sl, int64_t n_cells, hipStream_t st) {
+  AttemptWork W{};
+  W.st = m->d_st;
+  W.fnq = m->d_fnq;
+  W.H = m->d_H;
+  int cur = 0;
+  int64_t active = n_cells;
+  for (int launch = 0; active > 0; ++launch) {
+    LaunchShape sh;
+    int rc = shape_for(m, sl, active, (const void*)m->var->attempt, false, &sh);
+    if (rc) return rc;
+    W.first = launch == 0 ? 1 : 0;
+    W.act_in = m->d_act[cur];
+    W.n_in = m->d_cnt + cur;
+    W.act_out = m->d_act[cur ^ 1];
+    W.n_out = m->d_cnt + (cur ^ 1);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, W.n_out);
+    hipLaunchKernelGGL(m->var->attempt, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P, W);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(m->h_cnt, W.n_out, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e);
+    active = *m->h_cnt;
+    cur ^= 1;
+  }
+  return ROK4E_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -410,8 +559,10 @@ int rok4e_mech_destroy(rok4e_mech* m) {
   (void)hipGetDevice(&dev);
   (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
-  void* bufs[] = {m->d_image, m->d_queue, m->d_acc, m->d_rej, m->d_status};
+  void* bufs[] = {m->d_image, m->d_queue, m->d_acc, m->d_rej, m->d_status, m->d_st, m->d_fnq, m->d_H,
+                  m->d_act[0], m->d_act[1], m->d_cnt};
   for (void* b : bufs) (void)hipFree(b);
+  if (m->h_cnt) (void)hipHostFree(m->h_cnt);
   (void)hipSetDevice(dev);
   delete m;
   return ROK4E_OK;
@@ -531,6 +682,17 @@ int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
   P.rtol = rtol;
   P.atol = atol;
   LaunchShape sh;
+  if (m->opt.scheduling == ROK4E_PER_ATTEMPT) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return ROK4E_ECAPTURE;
+    rc = ensure_attempt_work(m, n_cells);
+    if (rc) return rc;
+    rc = run_per_attempt(m, P, sl, n_cells, st);
+    if (rc) return rc;
+    m->last_n = n_cells;
+    return ROK4E_OK;
+  }
   rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate, true, &sh);
   if (rc) return rc;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);

@@ -220,161 +220,172 @@ __device__ __forceinline__ void stage_solve(const double (&F)[ROWS], const doubl
   }
 }
 
-struct CellResult {
-  int status, accepted, rejected;
+// Integrator state of one cell between attempts (segment-uniform).  status: 0 running
+// or done, 1 attempt limit, 2 step size underflow, 3 invalid input.
+struct CellState {
+  double t, h, lerr_prev;   // time, step, ln of the last accepted error (0: err_prev = 1)
+  int attempts, accepted, rejected, steps_done, status, Meff, basis_valid, pad;
 };
 
-// Integrates the segment's cell over [0, dt] in place in u (Algorithm a:ROK4E with the
+__device__ __forceinline__ void cell_start(const Launch& P, CellState& c) {
+  c.t = 0.0;
+  c.h = P.fixed_steps > 0 ? P.dt / P.fixed_steps : (P.h0 > 0.0 ? P.h0 : P.dt);
+  c.lerr_prev = 0.0;
+  c.attempts = c.accepted = c.rejected = c.steps_done = c.status = c.Meff = c.basis_valid = c.pad = 0;
+}
+
+// True while the cell needs another attempt; reaching the attempt limit sets status 1.
+// Called once before every attempt and once after the last.
+__device__ __forceinline__ bool cell_running(const Launch& P, CellState& c) {
+  if (c.status != 0) return false;
+  const bool more = P.fixed_steps > 0 ? c.steps_done < P.fixed_steps : c.t < P.dt;
+  if (!more) return false;
+  const int max_att = P.max_attempts > 0 ? P.max_attempts : 1000000;
+  if (c.attempts >= max_att) {
+    c.status = 1;
+    return false;
+  }
+  return true;
+}
+
+// One attempt of Algorithm a:ROK4E on the segment's cell, in place in u and c, with the
 // readings: clipped last step, err_n = 1 before the first acceptance and updated on
-// acceptance, basis reused after a rejection, non-finite u* or err rejected).
+// acceptance, basis (fn, Q, the LDS copy of H, M_eff) reused after a rejection,
+// non-finite u* or err rejected.
 template <int L, int ROWS, int MMAX, class RT>
-__device__ CellResult integrate_cell(const DevMech& m, const MechLds& tab, const Launch& P,
-                                     double (&u)[ROWS], double p, const double (&s)[ROWS],
-                                     const SegLds<RT>& S, int lane) {
-  CellResult res{0, 0, 0};
+__device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& tab, const Launch& P,
+                                             double (&u)[ROWS], double p, const double (&s)[ROWS],
+                                             const SegLds<RT>& S, int lane, CellState& c,
+                                             double (&fn)[ROWS], double (&Q)[ROWS][MMAX]) {
   const int N = m.ns + 1;
   const double dt = P.dt;
   const double tiny = 16.0 * 2.220446049250313e-16 * dt;
-  const int max_att = P.max_attempts > 0 ? P.max_attempts : 1000000;
   const bool fixed = P.fixed_steps > 0;
-  double fn[ROWS], k1[ROWS], k2[ROWS], k3[ROWS], k4[ROWS];
-  double Q[ROWS][MMAX];
-  RT wbase[ROWS];
-  RhsBase base;
-  int Meff = 0;
-  bool basis_valid = false;
-  // ln of the last accepted error (err_prev = 1 before the first acceptance)
-  double t = 0.0, h = P.h0 > 0.0 ? P.h0 : dt, lerr_prev = 0.0;
-  if (fixed) h = dt / P.fixed_steps;
-  int attempts = 0, steps_done = 0;
+  double h = c.h;
+  bool last = false;
+  if (!fixed && h >= (dt - c.t) * (1.0 - 1e-12)) {
+    h = dt - c.t;
+    last = true;
+  }
+  if (!c.basis_valid) {
+    RT wbase[ROWS];
+    RhsBase base;
+    rhs_forced<L, ROWS, RT, true>(m, tab, u, p, s, fn, S, lane, &base, wbase);
+    c.Meff = arnoldi<L, ROWS, MMAX, RT>(m, tab, P, u, fn, base, wbase, Q, S, lane);
+    c.basis_valid = 1;
+  }
+  const int Meff = c.Meff;
+  // L = I - h gamma H, factored once per attempt.  Only the Hessenberg part of the LDS
+  // copy of H is written by the Arnoldi process; the rest is zero.
+  for (int i = 0; i < Meff; ++i)
+    for (int j = 0; j < Meff; ++j) {
+      const double hij = i <= j + 1 ? S.H[i * MMAX + j] : 0.0;
+      S.LU[i * MMAX + j] = (i == j ? 1.0 : 0.0) - h * G * hij;
+    }
+  lds_sync();
+  if (Meff > 0 && !lu_factor<MMAX>(S.LU, S.rdiag, S.piv, Meff)) {
+    ++c.attempts;
+    ++c.rejected;
+    c.h = h * 0.2;
+    if (c.h < tiny) c.status = 2;
+    return;
+  }
+  double k1[ROWS], k2[ROWS], k3[ROWS], k4[ROWS];
+  double corr[ROWS], F[ROWS], arg[ROWS], fs[ROWS];
+  RT wtmp[ROWS];
+  // Stage 1: F1 = f_n.
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) corr[i] = 0.0;
+  stage_solve<L, ROWS, MMAX>(fn, corr, k1, Q, Meff, S.LU, S.rdiag, S.piv);
+  // Stage 2: F2 = f(u + h a21 k1) + (g21/g) k1.
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A21 * k1[i]);
+  rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    corr[i] = (G21 / G) * k1[i];
+    F[i] = fs[i] + corr[i];
+  }
+  stage_solve<L, ROWS, MMAX>(F, corr, k2, Q, Meff, S.LU, S.rdiag, S.piv);
+  // Stage 3: F3 = f(u + h(a31 k1 + a32 k2)) + (g31 k1 + g32 k2)/g.
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A31 * k1[i] + A32 * k2[i]);
+  rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    corr[i] = (G31 * k1[i] + G32 * k2[i]) * (1.0 / G);
+    F[i] = fs[i] + corr[i];
+  }
+  stage_solve<L, ROWS, MMAX>(F, corr, k3, Q, Meff, S.LU, S.rdiag, S.piv);
+  // Stage 4 reuses f of stage 3 (a41 = a31, a42 = a32, a43 = 0).
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    corr[i] = (G41 * k1[i] + G42 * k2[i] + G43 * k3[i]) * (1.0 / G);
+    F[i] = fs[i] + corr[i];
+  }
+  stage_solve<L, ROWS, MMAX>(F, corr, k4, Q, Meff, S.LU, S.rdiag, S.piv);
 
-  while (fixed ? steps_done < P.fixed_steps : t < dt) {
-    if (attempts >= max_att) {
-      res.status = 1;
-      break;
-    }
-    bool last = false;
-    if (!fixed && h >= (dt - t) * (1.0 - 1e-12)) {
-      h = dt - t;
-      last = true;
-    }
-    if (!basis_valid) {
-      rhs_forced<L, ROWS, RT, true>(m, tab, u, p, s, fn, S, lane, &base, wbase);
-      Meff = arnoldi<L, ROWS, MMAX, RT>(m, tab, P, u, fn, base, wbase, Q, S, lane);
-      basis_valid = true;
-    }
-    // L = I - h gamma H, factored once per attempt.  Only the Hessenberg part of the
-    // LDS copy of H is written by the Arnoldi process; the rest is zero.
-    for (int i = 0; i < Meff; ++i)
-      for (int j = 0; j < Meff; ++j) {
-        const double hij = i <= j + 1 ? S.H[i * MMAX + j] : 0.0;
-        S.LU[i * MMAX + j] = (i == j ? 1.0 : 0.0) - h * G * hij;
-      }
-    lds_sync();
-    if (Meff > 0 && !lu_factor<MMAX>(S.LU, S.rdiag, S.piv, Meff)) {
-      ++attempts;
-      ++res.rejected;
-      h *= 0.2;
-      if (h < tiny) {
-        res.status = 2;
-        break;
-      }
-      continue;
-    }
-    double corr[ROWS], F[ROWS], arg[ROWS], fs[ROWS];
-    RT wtmp[ROWS];
-    // Stage 1: F1 = f_n.
+  double us[ROWS];
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i) corr[i] = 0.0;
-    stage_solve<L, ROWS, MMAX>(fn, corr, k1, Q, Meff, S.LU, S.rdiag, S.piv);
-    // Stage 2: F2 = f(u + h a21 k1) + (g21/g) k1.
+  for (int i = 0; i < ROWS; ++i) us[i] = u[i] + h * (B1 * k1[i] + B2 * k2[i] + B4 * k4[i]);
+  ++c.attempts;
+  if (fixed) {
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A21 * k1[i]);
-    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
+    for (int i = 0; i < ROWS; ++i) u[i] = us[i];
+    ++c.accepted;
+    ++c.steps_done;
+    c.basis_valid = 0;
+    return;
+  }
+  // Embedded error e = h sum (bh_j - b_j) k_j, weighted RMS over the N rows.
+  double en[ROWS][2], sums[2];
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      corr[i] = (G21 / G) * k1[i];
-      F[i] = fs[i] + corr[i];
-    }
-    stage_solve<L, ROWS, MMAX>(F, corr, k2, Q, Meff, S.LU, S.rdiag, S.piv);
-    // Stage 3: F3 = f(u + h(a31 k1 + a32 k2)) + (g31 k1 + g32 k2)/g.
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A31 * k1[i] + A32 * k2[i]);
-    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      corr[i] = (G31 * k1[i] + G32 * k2[i]) * (1.0 / G);
-      F[i] = fs[i] + corr[i];
-    }
-    stage_solve<L, ROWS, MMAX>(F, corr, k3, Q, Meff, S.LU, S.rdiag, S.piv);
-    // Stage 4 reuses f of stage 3 (a41 = a31, a42 = a32, a43 = 0).
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      corr[i] = (G41 * k1[i] + G42 * k2[i] + G43 * k3[i]) * (1.0 / G);
-      F[i] = fs[i] + corr[i];
-    }
-    stage_solve<L, ROWS, MMAX>(F, corr, k4, Q, Meff, S.LU, S.rdiag, S.piv);
-
-    double us[ROWS];
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) us[i] = u[i] + h * (B1 * k1[i] + B2 * k2[i] + B4 * k4[i]);
-    ++attempts;
-    if (fixed) {
-#pragma unroll
-      for (int i = 0; i < ROWS; ++i) u[i] = us[i];
-      ++res.accepted;
-      ++steps_done;
-      basis_valid = false;
-      continue;
-    }
-    // Embedded error e = h sum (bh_j - b_j) k_j, weighted RMS over the N rows.
-    double ss[ROWS], nb[ROWS];
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      const int r = (int)(i * L + lane);
-      ss[i] = 0.0;
-      nb[i] = 0.0;
-      if (r < N) {
-        const double e = h * (E1 * k1[i] + E2 * k2[i] + E3 * k3[i] + E4 * k4[i]);
-        const double sc = P.atol + P.rtol * fabs(us[i]);
-        const double ratio = e * rcp(sc);
-        ss[i] = ratio * ratio;
-        nb[i] = finite_(us[i]) ? 0.0 : 1.0;
-      }
-    }
-    double en[ROWS][2], sums[2];
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      en[i][0] = ss[i];
-      en[i][1] = nb[i];
-    }
-    seg_sum_rows_k<L, ROWS, 2>(en, sums);
-    double err = sqrt(sums[0] * (1.0 / N));
-    const double nbad = sums[1];
-    if (!finite_(err) || nbad != 0.0) err = __builtin_huge_val();
-    // PI controller, alpha = 0.7/4, beta = 0.4/4:
-    // 0.8 err_prev^0.1 / err^0.175 = 0.8 exp(0.1 ln err_prev - 0.175 ln err).
-    const double lerr = log(fmax(err, 1e-10));
-    const double fac = fmin(5.0, fmax(0.2, 0.8 * exp(0.1 * lerr_prev - 0.175 * lerr)));
-    const double hstar = h * fac;
-    if (err <= 1.0) {
-#pragma unroll
-      for (int i = 0; i < ROWS; ++i) u[i] = us[i];
-      t = last ? dt : t + h;
-      lerr_prev = lerr;
-      h = hstar;
-      ++res.accepted;
-      basis_valid = false;
-    } else {
-      h = hstar;
-      ++res.rejected;
-    }
-    if (t < dt && h < tiny) {
-      res.status = 2;
-      break;
+  for (int i = 0; i < ROWS; ++i) {
+    const int r = (int)(i * L + lane);
+    en[i][0] = 0.0;
+    en[i][1] = 0.0;
+    if (r < N) {
+      const double e = h * (E1 * k1[i] + E2 * k2[i] + E3 * k3[i] + E4 * k4[i]);
+      const double sc = P.atol + P.rtol * fabs(us[i]);
+      const double ratio = e * rcp(sc);
+      en[i][0] = ratio * ratio;
+      en[i][1] = finite_(us[i]) ? 0.0 : 1.0;
     }
   }
-  return res;
+  seg_sum_rows_k<L, ROWS, 2>(en, sums);
+  double err = sqrt(sums[0] * (1.0 / N));
+  const double nbad = sums[1];
+  if (!finite_(err) || nbad != 0.0) err = __builtin_huge_val();
+  // PI controller, alpha = 0.7/4, beta = 0.4/4:
+  // 0.8 err_prev^0.1 / err^0.175 = 0.8 exp(0.1 ln err_prev - 0.175 ln err).
+  const double lerr = log(fmax(err, 1e-10));
+  const double fac = fmin(5.0, fmax(0.2, 0.8 * exp(0.1 * c.lerr_prev - 0.175 * lerr)));
+  const double hstar = h * fac;
+  if (err <= 1.0) {
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) u[i] = us[i];
+    c.t = last ? dt : c.t + h;
+    c.lerr_prev = lerr;
+    ++c.accepted;
+    c.basis_valid = 0;
+  } else {
+    ++c.rejected;
+  }
+  c.h = hstar;
+  if (c.t < dt && c.h < tiny) c.status = 2;
+}
+
+// Integrates the segment's cell over [0, dt] in place in u (all attempts).
+template <int L, int ROWS, int MMAX, class RT>
+__device__ __forceinline__ CellState integrate_cell(const DevMech& m, const MechLds& tab,
+                                                    const Launch& P, double (&u)[ROWS], double p,
+                                                    const double (&s)[ROWS], const SegLds<RT>& S,
+                                                    int lane) {
+  CellState c;
+  cell_start(P, c);
+  double fn[ROWS], Q[ROWS][MMAX];
+  while (cell_running(P, c)) cell_attempt<L, ROWS, MMAX, RT>(m, tab, P, u, p, s, S, lane, c, fn, Q);
+  return c;
 }
 
 // Loads a cell's rows (Y, T, forcing) for this lane; returns false if the input is not a

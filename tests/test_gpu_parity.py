@@ -191,6 +191,28 @@ def test_layouts_agree_and_runs_are_deterministic(R, orc):
         assert mx <= 4 * env["env_max"] + 0.05
 
 
+@pytest.mark.parametrize("cfg,n", [(1, 300), (3, 512)])
+def test_per_attempt_schedule_is_bitwise_identical(R, cfg, n):
+    """One launch per attempt with the cell state carried in device memory performs the
+    same arithmetic as the persistent kernel: identical states and counts, also for an
+    invalid cell, the attempt limit and fixed steps."""
+    w = synth.workload(cfg, a_scale=A_SCALE)
+    idx = synth.stratified_sample(w.states.T, n, 300 + cfg)
+    st = w.states.subset(idx)
+    T = st.T.copy()
+    T[3] = np.nan
+    st = synth.States(st.Y, T, st.p)
+    for kw in (dict(max_attempts=MAX_ATT), dict(max_attempts=3), dict(fixed_steps=2)):
+        outs = []
+        for sched in (R.PERSISTENT, R.PER_ATTEMPT):
+            m = R.Mech(w.mech, M=w.M, scheduling=sched, **kw)
+            outs.append(gpu_integrate(m, st, w.dt, w.rtol, w.atol))
+            m.close()
+        assert outs[0][4][3] == 3
+        for a, b in zip(*outs):
+            np.testing.assert_array_equal(a, b)
+
+
 def test_edge_cases(R, orc):
     import torch
     w = synth.workload(1, a_scale=A_SCALE, n_cells=5)
