@@ -136,6 +136,16 @@ int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* mech, double* Y, double*
                            const double* p, const double* S, double dt, double rtol,
                            double atol, void* stream);
 
+/* Launch tuning: integrates a copy of the given batch (Y, T, p as for rok4e_integrate;
+ * the caller's arrays are not modified) once per waves-per-block choice 1..4 with the
+ * handle's other options, times each with HIP events after a warm-up run, and keeps the
+ * fastest in the handle's options (waves_per_block; blocks_per_cu automatic).  These
+ * choices do not change any result bit.  Writes the choice and its time (ms) when the
+ * pointers are not NULL.  Allocates scratch for one copy of Y and T and synchronises
+ * the stream; ROK4E_ECAPTURE inside a stream capture, ROK4E_EINVAL for n_cells == 0. */
+int rok4e_tune(int64_t n_cells, rok4e_mech* mech, const double* Y, const double* T, const double* p,
+               double dt, double rtol, double atol, int32_t* best_waves, float* best_ms, void* stream);
+
 /* Evaluates the reactor right-hand side f(u) for every cell (Sec. 4.4, e:cv_reactor):
  * dY[k * n_cells + c], dT[c].  Inputs are not modified. */
 int rok4e_rhs(int64_t n_cells, rok4e_mech* mech, const double* Y, const double* T, const double* p,

@@ -708,6 +708,56 @@ int rok4e_integrate(int64_t n_cells, rok4e_mech* m, double* Y, double* T, const 
   return rok4e_integrate_forced(n_cells, m, Y, T, p, nullptr, dt, rtol, atol, stream);
 }
 
+int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T, const double* p,
+               double dt, double rtol, double atol, int32_t* best_waves, float* best_ms, void* stream) {
+  int rc = check_state_args(n_cells, m, Y, T, p);
+  if (rc) return rc;
+  if (n_cells == 0) return ROK4E_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ROK4E_ECAPTURE;
+  const size_t ny = (size_t)m->ns * n_cells;
+  double *Y2 = nullptr, *T2 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc((void**)&Y2, ny * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&T2, n_cells * sizeof(double));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const rok4e_options saved = m->opt;
+  int best = 0;
+  float best_t = 0.0f;
+  for (int wpb = 1; e == hipSuccess && rc == ROK4E_OK && wpb <= 4; ++wpb) {
+    m->opt.waves_per_block = wpb;
+    m->opt.blocks_per_cu = 0;
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2 && e == hipSuccess && rc == ROK4E_OK; ++rep) {   // first: warm-up
+      e = hipMemcpyAsync(Y2, Y, ny * sizeof(double), hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(T2, T, n_cells * sizeof(double), hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e == hipSuccess) rc = rok4e_integrate(n_cells, m, Y2, T2, p, dt, rtol, atol, stream);
+      if (e == hipSuccess && rc == ROK4E_OK) e = hipEventRecord(e1, st);
+      if (e == hipSuccess && rc == ROK4E_OK) e = hipEventSynchronize(e1);
+      if (e == hipSuccess && rc == ROK4E_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (e == hipSuccess && rc == ROK4E_OK && (best == 0 || ms < best_t)) {
+      best = wpb;
+      best_t = ms;
+    }
+  }
+  m->opt = saved;
+  if (e == hipSuccess && rc == ROK4E_OK) {
+    m->opt.waves_per_block = best;
+    if (best_waves) *best_waves = best;
+    if (best_ms) *best_ms = best_t;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(Y2);
+  (void)hipFree(T2);
+  if (e != hipSuccess) return hip_fail(e);
+  return rc;
+}
+
 int rok4e_rhs(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T, const double* p,
               double* dY, double* dT, void* stream) {
   int rc = check_state_args(n_cells, m, Y, T, p);

@@ -24,7 +24,7 @@ CELL_OK, CELL_MAX_ATTEMPTS, CELL_STEP_UNDERFLOW, CELL_BAD_INPUT = 0, 1, 2, 3
 
 EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "rok4e_set_options",
            "rok4e_get_options", "rok4e_reserve", "rok4e_integrate", "rok4e_integrate_forced",
-           "rok4e_rhs", "rok4e_arnoldi", "rok4e_get_stats", "rok4e_cell_stats_ptr",
+           "rok4e_tune", "rok4e_rhs", "rok4e_arnoldi", "rok4e_get_stats", "rok4e_cell_stats_ptr",
            "rok4e_copy_cell_stats", "rok4e_strerror"]
 
 
@@ -77,6 +77,8 @@ def load():
         lib.rok4e_reserve.argtypes = [vp, i64]
         lib.rok4e_integrate.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_forced.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
+        lib.rok4e_tune.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_float), vp]
         lib.rok4e_rhs.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
         lib.rok4e_arnoldi.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.rok4e_get_stats.argtypes = [vp, C.POINTER(Stats), vp]
@@ -170,6 +172,16 @@ class Mech:
                                            float(rtol), float(atol), _stream(stream))
         _check(rc, "rok4e_integrate")
         self.n_last = n
+
+    def tune(self, Y, T, p, dt, rtol, atol, stream=None) -> tuple[int, float]:
+        """rok4e_tune: picks the fastest waves-per-block on a copy of this batch; returns
+        (waves_per_block, ms)."""
+        n = int(T.shape[0])
+        wv, ms = C.c_int32(0), C.c_float(0.0)
+        _check(load().rok4e_tune(n, self._h, _ptr(Y), _ptr(T), _ptr(p), float(dt), float(rtol), float(atol),
+                                 C.byref(wv), C.byref(ms), _stream(stream)), "rok4e_tune")
+        self.opts.waves_per_block = wv.value
+        return wv.value, ms.value
 
     def rhs(self, Y, T, p, dY, dT, stream=None):
         n = int(T.shape[0])

@@ -213,6 +213,55 @@ def test_per_attempt_schedule_is_bitwise_identical(R, cfg, n):
             np.testing.assert_array_equal(a, b)
 
 
+def test_graph_capture_replays_match_eager(R):
+    """The persistent launch (queue reset kernel + integrator, no memset node) captured
+    in a HIP graph: several replays, each on fresh inputs copied in eagerly between them,
+    equal the eager call bit for bit."""
+    import torch
+    w = synth.workload(1, a_scale=A_SCALE, n_cells=400)
+    st = w.states
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    m.reserve(st.n_cells)
+    Y0, T0, p = dev_state(st)
+    Ye, Te = Y0.clone(), T0.clone()
+    m.integrate(Ye, Te, p, w.dt, w.rtol, w.atol)
+    torch.cuda.synchronize()
+    Y, T = Y0.clone(), T0.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            m.integrate(Y, T, p, w.dt, w.rtol, w.atol)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        Y.copy_(Y0)
+        T.copy_(T0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Y, Ye) and torch.equal(T, Te), f"replay {rep}"
+    m.close()
+
+
+def test_tune_leaves_inputs_and_results_unchanged(R):
+    import torch
+    w = synth.workload(2, a_scale=A_SCALE, n_cells=2048)
+    st = w.states
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    before = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    Y, T, p = dev_state(st)
+    wv, ms = m.tune(Y, T, p, w.dt, w.rtol, w.atol)
+    assert 1 <= wv <= 4 and ms > 0.0
+    assert m.get_options().waves_per_block == wv
+    np.testing.assert_array_equal(Y.cpu().numpy(), st.Y)
+    np.testing.assert_array_equal(T.cpu().numpy(), st.T)
+    after = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    for a, b in zip(before, after):
+        np.testing.assert_array_equal(a, b)
+    m.close()
+
+
 def test_edge_cases(R, orc):
     import torch
     w = synth.workload(1, a_scale=A_SCALE, n_cells=5)
