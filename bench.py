@@ -8,12 +8,14 @@ mechanism; the literal draw is too stiff to integrate, see the design notes).
 
 Prints one JSON line: FP64 cell-integrations/s as `value`, the mixed-precision figure
 and speed-up beside it, the roofline of the integration kernel (algorithmic FP64
-operations / kernel time against the FP64 vector peak) and the CPU oracle timed on a
-bounded sample on this host.
+operations / kernel time against the FP64 vector peak), the standalone right-hand-side
+and Arnoldi kernels against the same peak, persistent vs per-attempt scheduling on the
+262,144-cell bimodal batch, and the CPU oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -29,6 +31,10 @@ METRIC = "ROK4E cell-integrations/s at 53 species, FP64 vs mixed, % of roofline"
 A_SCALE = 1e-8
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
+# HBM bytes of one integration launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (scaled by a plain device copy of known size); used only while the kernel sources
+# hash to the value recorded with the measurement.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_integrate_53sp_flame.json")
 
 
 def log(*a):
@@ -45,6 +51,39 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources, the public header and the build flags."""
+    from paper_1712_00953_amd import build
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1712_00953_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)) + [os.path.join(ROOT, "include", "rok4e.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    h.update(" ".join(build.FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d
+
+
+def timed_events(torch, stream, fn, reps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) * 1e-3 for a, b in ev]
+
+
 def run_gpu(w, precision, steps, warmup, R, torch):
     from paper_1712_00953_amd import workmodel
     st = w.states
@@ -57,7 +96,7 @@ def run_gpu(w, precision, steps, warmup, R, torch):
     copies = [(Y0.clone(), T0.clone()) for _ in range(warmup + steps)]
     m = R.Mech(w.mech, M=w.M, precision=precision, max_attempts=200000)
     m.reserve(n)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.current_stream()   # the stream the library launches on
     for i in range(warmup):
         m.integrate(copies[i][0], copies[i][1], p, w.dt, w.rtol, w.atol)
     torch.cuda.synchronize()
@@ -85,6 +124,70 @@ def run_gpu(w, precision, steps, warmup, R, torch):
                 transcendentals=ops["transcendentals"],
                 tflops=ops["flops"] / kavg * 1e-12,
                 bytes=workmodel.state_bytes(w.mech, n))
+
+
+def run_subsystems(w, R, torch, reps=5):
+    """The right-hand side and the Arnoldi basis (f(u_n), M JVPs, Gram-Schmidt) as
+    standalone kernels over the same batch, against the FP64 vector peak."""
+    from paper_1712_00953_amd import workmodel
+    st = w.states
+    n, N, M = st.n_cells, w.mech.n_species + 1, w.M
+    dev = torch.device("cuda:0")
+    Y = torch.tensor(st.Y, dtype=torch.float64, device=dev)
+    T = torch.tensor(st.T, dtype=torch.float64, device=dev)
+    p = torch.tensor(st.p, dtype=torch.float64, device=dev)
+    dY, dT = torch.empty_like(Y), torch.empty_like(T)
+    Q = torch.empty(n * M * N, dtype=torch.float64, device=dev)
+    H = torch.empty(n * M * M, dtype=torch.float64, device=dev)
+    Me = torch.empty(n, dtype=torch.int32, device=dev)
+    m = R.Mech(w.mech, M=M)
+    stream = torch.cuda.current_stream()
+    m.rhs(Y, T, p, dY, dT)
+    m.arnoldi(Y, T, p, Q, H, Me)
+    t_rhs = float(np.median(timed_events(torch, stream, lambda: m.rhs(Y, T, p, dY, dT), reps)))
+    t_arn = float(np.median(timed_events(torch, stream, lambda: m.arnoldi(Y, T, p, Q, H, Me), reps)))
+    m.close()
+    a = workmodel.attempt_ops(w.mech, M)
+    out = {}
+    for name, t, ops in (("rhs", t_rhs, a["rhs"]), ("arnoldi_basis", t_arn, a["basis"])):
+        tf = ops * n / t * 1e-12
+        out[name] = {"cells_per_s": n / t, "kernel_ms": t * 1e3, "algorithmic_flops_per_cell": ops,
+                     "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS}
+    return out
+
+
+def run_schedules(R, torch, synth):
+    """Persistent queue vs one launch per attempt on the 262,144-cell bimodal batch."""
+    w = synth.workload(3, a_scale=A_SCALE)
+    st = w.states
+    n = st.n_cells
+    dev = torch.device("cuda:0")
+    Y0 = torch.tensor(st.Y, dtype=torch.float64, device=dev)
+    T0 = torch.tensor(st.T, dtype=torch.float64, device=dev)
+    p = torch.tensor(st.p, dtype=torch.float64, device=dev)
+    out, res = {}, {}
+    for name, sched in (("persistent", R.PERSISTENT), ("per_attempt", R.PER_ATTEMPT)):
+        m = R.Mech(w.mech, M=w.M, max_attempts=200000, scheduling=sched)
+        m.reserve(n)
+        Y, T = Y0.clone(), T0.clone()
+        m.integrate(Y, T, p, w.dt, w.rtol, w.atol)
+        Y.copy_(Y0)
+        T.copy_(T0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.integrate(Y, T, p, w.dt, w.rtol, w.atol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s = m.stats()
+        m.close()
+        res[name] = (Y, T)
+        out[name] = {"cells_per_s": n / el, "ms": el * 1e3, "attempts": s["accepted"] + s["rejected"],
+                     "max_attempts_cell": s["max_attempts"]}
+    out["speedup_persistent"] = out["persistent"]["cells_per_s"] / out["per_attempt"]["cells_per_s"]
+    out["bitwise_equal"] = bool(torch.equal(res["persistent"][0], res["per_attempt"][0])
+                                and torch.equal(res["persistent"][1], res["per_attempt"][1]))
+    out["workload"] = w.name + " (pre-exponential factors x 1e-8)"
+    return out
 
 
 def run_cpu_baseline(w, target_s=10.0):
@@ -115,11 +218,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the standalone subsystem kernels and the scheduling comparison")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the measurement, copy 1 GiB device-to-device (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
+    ap.add_argument("--print-source-hash", action="store_true",
+                    help="print the kernel source hash that a traffic measurement must carry")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the reaction substep is cell-parallel and "
               f"this build runs on a single MI355X; --gpus {args.gpus} is not supported.",
@@ -141,6 +251,14 @@ def main():
     if not args.no_mixed:
         mixed = run_gpu(w, R.MIXED, args.steps, args.warmup, R, torch)
         log(f"mixed: {mixed['cells_per_s']:.4e} cells/s, {mixed['ms_per_step']:.2f} ms/step")
+    subsystems = schedules = None
+    if not args.no_extras:
+        subsystems = run_subsystems(w, R, torch)
+        log("subsystems: " + ", ".join(f"{k} {v['kernel_ms']:.3f} ms ({v['frac'] * 100:.1f}% of FP64 peak)"
+                                       for k, v in subsystems.items()))
+        schedules = run_schedules(R, torch, synth)
+        log(f"schedules: persistent {schedules['persistent']['ms']:.1f} ms, per-attempt "
+            f"{schedules['per_attempt']['ms']:.1f} ms, bitwise equal {schedules['bitwise_equal']}")
     if args.copy_calibration:
         # write a 1 GiB buffer, evict it from the caches with a second one, then copy it:
         # the copy kernel reads 1 GiB and writes 1 GiB
@@ -158,6 +276,7 @@ def main():
         cpu = run_cpu_baseline(w, args.cpu_seconds)
         log(f"cpu oracle: {cpu['value']:.4e} cells/s ({cpu['sample']})")
 
+    traffic = load_traffic()
     achieved = fp64["tflops"]
     out = {
         "metric": METRIC,
@@ -178,7 +297,8 @@ def main():
                    "atol": w.atol, "a_scale": A_SCALE, "precision": "fp64",
                    "attempts_per_step": fp64["attempts"], "max_attempts_cell": fp64["max_attempts"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
                      "kernel": "k_integrate (persistent ROK4E integration)",
                      "kernel_ms": fp64["kernel_s"] * 1e3,
                      "algorithmic_flops_per_launch": fp64["flops"],
@@ -186,12 +306,20 @@ def main():
                      "state_bytes_per_launch": fp64["bytes"],
                      "hbm_frac_algorithmic": fp64["bytes"] / fp64["kernel_s"] / 1e9 / PEAK_HBM_GBS},
     }
+    if traffic:
+        out["roofline"]["traffic_detail"] = {k: traffic[k] for k in (
+            "fetch_bytes_per_launch", "write_bytes_per_launch", "copy_scale_fetch", "copy_scale_write",
+            "profile")}
     if mixed is not None:
         out["mixed"] = {"value": mixed["cells_per_s"], "unit": "cell-integrations/s",
                         "ms_per_step": mixed["ms_per_step"], "dtype": "f32 rates / f64 state",
                         "speedup_vs_fp64": mixed["cells_per_s"] / fp64["cells_per_s"],
                         "attempts_per_step": mixed["attempts"],
                         "tflops_fp64_equivalent": mixed["tflops"]}
+    if subsystems is not None:
+        out["subsystems"] = subsystems
+    if schedules is not None:
+        out["schedules"] = schedules
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

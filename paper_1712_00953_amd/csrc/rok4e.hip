@@ -317,8 +317,9 @@ const Variant* pick_variant(int ns, const rok4e_options& o) {
   return best;
 }
 
-// Per-segment LDS: species arrays [3][LP] and the rate-constant pairs [NRP] in the rate
-// type; H, LU [MMAX^2], 1/diag(U) [MMAX] in FP64; piv [MMAX].
+// Per-segment LDS: concentrations and increments [2][LP] and the rate-constant pairs
+// [NRP] in the rate type, production accumulators [LP], H, LU [MMAX^2] and 1/diag(U)
+// [MMAX] in FP64; piv [MMAX].
 struct SegLayout {
   int bytes, off_k, off_H, off_LU, off_rdiag, off_piv;
 };
@@ -333,7 +334,7 @@ SegLayout seg_layout(int nr, const Variant& v) {
   const int rt = rate_bytes(v.prec);
   const int lp = v.L * v.rows;
   SegLayout s{};
-  int off = al16(3 * lp * rt);
+  int off = al16(2 * lp * rt + lp * 8);
   s.off_k = off;
   off = al16(off + n_rx_padded(nr) * 2 * rt);
   s.off_H = off;

@@ -312,16 +312,24 @@ __device__ __forceinline__ double rcp(double x) {
 
 // -------------------------------------------------------- right-hand side ----
 
-// Per-segment LDS scratch of the right-hand side.  spc holds three arrays of LP entries:
-// concentrations of the base state, their increments (difference evaluation) and the
-// production accumulators, so species k sits at spc[k], spc[LP + k], spc[2 LP + k]
-// (8-byte stride: consecutive species fall in different LDS banks).  Entry ns is the
-// absent reaction slot: concentration 1, increment 0, accumulator never read.
+// Per-segment LDS scratch of the right-hand side.  spc holds the concentrations of the
+// base state and their increments (difference evaluation), LP entries each in the rate
+// type, followed by LP FP64 production accumulators: species k sits at spc[k],
+// spc[LP + k] and acc(k) (consecutive species fall in different LDS banks).  The
+// accumulators are FP64 in both precisions.  Entry ns is the absent reaction slot:
+// concentration 1, increment 0, accumulator never read.
 template <class RT>
 struct RhsLds {
-  RT* spc;                        // [3][LP]
+  RT* spc;                        // [2][LP] rate type, then double [LP]
   typename Pair2<RT>::type* k;    // [NRP] (k_f, k_r) of the base state
 };
+
+// Accumulator of the species at byte offset off (species x sizeof(RT)) of the concentration
+// array that starts at rb.
+template <int LP, class RT>
+__device__ __forceinline__ double* acc_at(char* rb, unsigned off) {
+  return (double*)(rb + 2 * LP * sizeof(RT) + off * (sizeof(double) / sizeof(RT)));
+}
 
 // Cell-uniform quantities of a base evaluation f(u), kept for the difference evaluation.
 struct RhsBase {
@@ -365,11 +373,12 @@ __device__ __forceinline__ void lds_add(RT* p, RT v) {
 // reaction: a repeated species receives the term twice, a species on both sides -q and
 // +q.  An absent slot adds into the accumulator of entry ns, which is never read.
 template <int LP, class RT>
-__device__ __forceinline__ void scatter_rate(char* rb, uint2 o, RT q) {
-  lds_add((RT*)(rb + (o.x & 0xFFFFu)) + 2 * LP, -q);
-  lds_add((RT*)(rb + (o.x >> 16)) + 2 * LP, -q);
-  lds_add((RT*)(rb + (o.y & 0xFFFFu)) + 2 * LP, q);
-  lds_add((RT*)(rb + (o.y >> 16)) + 2 * LP, q);
+__device__ __forceinline__ void scatter_rate(char* rb, uint2 o, RT qr) {
+  const double q = (double)qr;
+  lds_add(acc_at<LP, RT>(rb, o.x & 0xFFFFu), -q);
+  lds_add(acc_at<LP, RT>(rb, o.x >> 16), -q);
+  lds_add(acc_at<LP, RT>(rb, o.y & 0xFFFFu), q);
+  lds_add(acc_at<LP, RT>(rb, o.y >> 16), q);
 }
 
 // f(u) of one cell held by a segment (Sec. 4.4, e:cv_reactor, constant-pressure
@@ -403,7 +412,7 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
     const int r = s * L + lane;
     if (r < ns) {
       S.spc[r] = (RT)(1e-6 * rho * u[s] * t.invW[r]);
-      S.spc[2 * LP + r] = (RT)0;
+      *acc_at<LP, RT>((char*)S.spc, r * sizeof(RT)) = 0.0;
     }
   }
   const double lnT = log(T);
@@ -427,7 +436,7 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const RT wk = r < ns ? (RT)1e6 * S.spc[2 * LP + r] : (RT)0;
+    const RT wk = r < ns ? (RT)(1e6 * *acc_at<LP, RT>((char*)S.spc, r * sizeof(RT))) : (RT)0;
     w[s] = wk;
     f[s] = (double)((RT)t.W[r] * wk * (RT)invrho);
     const RT hk = (RT)(t.hf[r] + t.cp[r] * (T - kTref));
@@ -480,7 +489,7 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
     const int r = s * L + lane;
     if (r < ns) {
       S.spc[LP + r] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * t.invW[r]);
-      S.spc[2 * LP + r] = (RT)0;
+      *acc_at<LP, RT>((char*)S.spc, r * sizeof(RT)) = 0.0;
     }
   }
   const double dlnT = log1p_small(dT * B.invT);
@@ -512,7 +521,8 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const double dw = r < ns ? 1e6 * (double)S.spc[2 * LP + r] : 0.0, wk = (double)w[s];
+    const double dw = r < ns ? 1e6 * *acc_at<LP, RT>((char*)S.spc, r * sizeof(RT)) : 0.0;
+    const double wk = (double)w[s];
     df[s] = t.W[r] * (dw * invrho1 - wk * drho * B.invrho * invrho1);
     const double hk = t.hf[r] + t.cp[r] * (T - kTref), dhk = t.cp[r] * dT;
     ph[s] = t.W[r] * ((hk + dhk) * dw + dhk * wk);

@@ -52,7 +52,10 @@ def attempt_ops(mech, M: int) -> dict:
     retry = 2 * cf + lu + stages + finish
     trans_new = (Me + 3) * tf + 2 + Me
     trans_retry = 2 * tf + 2
-    return dict(new=new, retry=retry, trans_new=trans_new, trans_retry=trans_retry, rhs=cf)
+    # the basis alone: f(u_n), the M_eff Jacobian-vector products and the Gram-Schmidt work
+    basis = cf + Me * jvp + arnoldi
+    return dict(new=new, retry=retry, trans_new=trans_new, trans_retry=trans_retry, rhs=cf,
+                basis=basis)
 
 
 def batch_ops(mech, M: int, accepted: int, rejected: int) -> dict:
