@@ -12,6 +12,7 @@
 
 #include "rok4e.h"
 #include "rok4e_integrator.hpp"
+#include "rok4e_placement.hpp"
 
 namespace rok4e {
 
@@ -349,6 +350,9 @@ SegLayout seg_layout(int nr, const Variant& v) {
   return s;
 }
 
+// Annealing steps of the reaction / species placement (about 10 us each at 53 species).
+constexpr long kPlacementSteps = 60000;
+
 // Builds (or reuses) the table image for the handle's current layout and rate type; see
 // DevMech.
 int ensure_image(rok4e_mech* m) {
@@ -358,18 +362,28 @@ int ensure_image(rok4e_mech* m) {
   if (m->image_key == key && m->d_image) return ROK4E_OK;
   const int ns = m->ns, nr = m->nr;
   const int nrp = n_rx_padded(nr);
+  // placement of reactions on (iteration, lane) positions and of species in LDS
+  std::vector<int> slots(4 * (size_t)nr);
+  for (int j = 0; j < nr; ++j) {
+    const int sl[4] = {m->reac[2 * j], m->reac[2 * j + 1], m->prod[2 * j], m->prod[2 * j + 1]};
+    for (int a = 0; a < 4; ++a) slots[4 * j + a] = sl[a] < 0 ? ns : sl[a];
+  }
+  PlacementSearch search(ns, nr, slots, m->var->L, rb);
+  const Placement pl = search.run(kPlacementSteps, 0x5eed0000ull + (uint64_t)key);
   const int off_spec = al16(3 * nrp * 16);
   const int off_rxo = al16(off_spec + 4 * lp * 8);
-  const int bytes = al16(off_rxo + nrp * 8);
+  const int off_spos = al16(off_rxo + nrp * 8);
+  const int bytes = al16(off_spos + lp * 4);
   std::vector<char> img(bytes, 0);
   // (ln A_f, ln A_r), (b_f, E_f), (b_r, E_r); m->par holds ln A_f, b_f, E_f, ln A_r,
   // b_r, E_r, each [nr]
   double* par = (double*)img.data();
   const int pair_q[3][2] = {{0, 3}, {1, 2}, {4, 5}};
   for (int a = 0; a < 3; ++a)
-    for (int j = 0; j < nr; ++j) {
-      par[(a * nrp + j) * 2] = m->par[pair_q[a][0] * nr + j];
-      par[(a * nrp + j) * 2 + 1] = m->par[pair_q[a][1] * nr + j];
+    for (int q = 0; q < nr; ++q) {
+      const int j = pl.order[q];
+      par[(a * nrp + q) * 2] = m->par[pair_q[a][0] * nr + j];
+      par[(a * nrp + q) * 2 + 1] = m->par[pair_q[a][1] * nr + j];
     }
   double* sp = (double*)(img.data() + off_spec);
   for (int r = 0; r < lp; ++r) {
@@ -380,17 +394,20 @@ int ensure_image(rok4e_mech* m) {
     sp[3 * lp + r] = spc ? m->hf[r] : 0.0;
   }
   uint32_t* rxo = (uint32_t*)(img.data() + off_rxo);
-  auto off = [&](int k) { return (uint32_t)((k < 0 ? ns : k) * rb); };
-  for (int j = 0; j < nr; ++j) {
-    rxo[2 * j] = off(m->reac[2 * j]) | off(m->reac[2 * j + 1]) << 16;
-    rxo[2 * j + 1] = off(m->prod[2 * j]) | off(m->prod[2 * j + 1]) << 16;
+  auto off = [&](int k) { return (uint32_t)(pl.pos[k] * rb); };
+  for (int q = 0; q < nr; ++q) {
+    const int* sl = &slots[4 * (size_t)pl.order[q]];
+    rxo[2 * q] = off(sl[0]) | off(sl[1]) << 16;
+    rxo[2 * q + 1] = off(sl[2]) | off(sl[3]) << 16;
   }
+  int* spos = (int*)(img.data() + off_spos);
+  for (int r = 0; r < lp; ++r) spos[r] = r < ns ? pl.pos[r] : ns;
   if (m->d_image) (void)hipFree(m->d_image);
   m->d_image = nullptr;
   hipError_t e = hipMalloc(&m->d_image, bytes);
   if (e == hipSuccess) e = hipMemcpy(m->d_image, img.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e);
-  m->dm = DevMech{ns, nr, nrp, lp, off_spec, off_rxo, bytes, (const int4*)m->d_image};
+  m->dm = DevMech{ns, nr, nrp, lp, off_spec, off_rxo, off_spos, bytes, (const int4*)m->d_image};
   m->image_key = key;
   return ROK4E_OK;
 }

@@ -47,13 +47,17 @@ constexpr double E1 = BH1 - B1, E2 = BH2 - B2, E3 = BH3 - 0.0, E4 = 0.0 - B4;
 //   double2 bEf[NRP]     (b_f, E_f)
 //   double2 bEr[NRP]     (b_r, E_r)
 //   double  spec[4][LP]  W, 1/W, c_p, h_f per state row (zeros/ones past the species)
-//   uint2   rxo[NRP]     byte offsets (species x size of the rate type) of the species of
-//                        reaction j in the per-cell species arrays: .x = reac0 | reac1 << 16,
-//                        .y = prod0 | prod1 << 16; an absent slot holds the offset of
-//                        entry ns (concentration 1, increment 0)
+//   uint2   rxo[NRP]     byte offsets (LDS position x size of the rate type) of the species
+//                        of reaction j in the per-cell species arrays: .x = reac0 | reac1
+//                        << 16, .y = prod0 | prod1 << 16; an absent slot holds the offset
+//                        of entry ns (concentration 1, increment 0)
+//   int     spos[LP]     LDS position of the species of state row r (ns past the species)
+// Reaction j of the tables is the mechanism's reaction order[j] and species k sits at LDS
+// position pos[k] (host-side placement that spreads LDS bank traffic; it changes only the
+// order of the production sums).
 struct DevMech {
   int ns, nr, nrp, lp;
-  int off_spec, off_rxo, image_bytes;
+  int off_spec, off_rxo, off_spos, image_bytes;
   const int4* image;
 };
 
@@ -62,6 +66,7 @@ struct MechLds {
   const double2* lnA; const double2* bEf; const double2* bEr;
   const double* W; const double* invW; const double* cp; const double* hf;
   const uint2* rxo;
+  const int* spos;
 };
 
 // A pair of rate-type values (the forward and reverse rate constants of a reaction).
@@ -93,6 +98,7 @@ __device__ __forceinline__ MechLds load_mech_lds(const DevMech& m, char* lds) {
   const double* sp = (const double*)(lds + m.off_spec);
   t.W = sp; t.invW = sp + m.lp; t.cp = sp + 2 * m.lp; t.hf = sp + 3 * m.lp;
   t.rxo = (const uint2*)(lds + m.off_rxo);
+  t.spos = (const int*)(lds + m.off_spos);
   return t;
 }
 
@@ -411,8 +417,9 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
     if (r < ns) {
-      S.spc[r] = (RT)(1e-6 * rho * u[s] * t.invW[r]);
-      *acc_at<LP, RT>((char*)S.spc, r * sizeof(RT)) = 0.0;
+      const int q = t.spos[r];
+      S.spc[q] = (RT)(1e-6 * rho * u[s] * t.invW[r]);
+      *acc_at<LP, RT>((char*)S.spc, q * sizeof(RT)) = 0.0;
     }
   }
   const double lnT = log(T);
@@ -436,7 +443,7 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const RT wk = r < ns ? (RT)(1e6 * *acc_at<LP, RT>((char*)S.spc, r * sizeof(RT))) : (RT)0;
+    const RT wk = r < ns ? (RT)(1e6 * *acc_at<LP, RT>((char*)S.spc, t.spos[r] * sizeof(RT))) : (RT)0;
     w[s] = wk;
     f[s] = (double)((RT)t.W[r] * wk * (RT)invrho);
     const RT hk = (RT)(t.hf[r] + t.cp[r] * (T - kTref));
@@ -488,8 +495,9 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
     if (r < ns) {
-      S.spc[LP + r] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * t.invW[r]);
-      *acc_at<LP, RT>((char*)S.spc, r * sizeof(RT)) = 0.0;
+      const int q = t.spos[r];
+      S.spc[LP + q] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * t.invW[r]);
+      *acc_at<LP, RT>((char*)S.spc, q * sizeof(RT)) = 0.0;
     }
   }
   const double dlnT = log1p_small(dT * B.invT);
@@ -521,7 +529,7 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const double dw = r < ns ? 1e6 * *acc_at<LP, RT>((char*)S.spc, r * sizeof(RT)) : 0.0;
+    const double dw = r < ns ? 1e6 * *acc_at<LP, RT>((char*)S.spc, t.spos[r] * sizeof(RT)) : 0.0;
     const double wk = (double)w[s];
     df[s] = t.W[r] * (dw * invrho1 - wk * drho * B.invrho * invrho1);
     const double hk = t.hf[r] + t.cp[r] * (T - kTref), dhk = t.cp[r] * dT;
