@@ -25,6 +25,7 @@
 #ifndef ROK4E_H
 #define ROK4E_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -145,6 +146,45 @@ int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* mech, double* Y, double*
  * the stream; ROK4E_ECAPTURE inside a stream capture, ROK4E_EINVAL for n_cells == 0. */
 int rok4e_tune(int64_t n_cells, rok4e_mech* mech, const double* Y, const double* T, const double* p,
                double dt, double rtol, double atol, int32_t* best_waves, float* best_ms, void* stream);
+
+/* ---- Splitting around the reaction substep (Sec. 3.3) ------------------------------
+ * Model transport operator on a periodic nx x ny x nz grid of cubic cells (cell
+ * c = x + nx (y + ny z), the cell index of the state arrays): advection with velocity vel
+ * along x and diffusion with diffusivity diff, second-order central differences, applied
+ * to every state row (mass fractions and temperature):
+ *   T(U)_r = -vel (U_{x+1} - U_{x-1}) / (2 dx) + diff (sum of six neighbours - 6 U) / dx^2 */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx;     /* m, > 0 */
+  double vel;    /* m/s */
+  double diff;   /* m^2/s, >= 0 */
+} rok4e_grid;
+
+#define ROK4E_SPLIT_SIMPLER 0  /* Simpler balanced splitting, e:simpler_balanced */
+#define ROK4E_SPLIT_STRANG 1   /* Strang splitting, e:strang_t1..e:strang_t3 (control) */
+
+/* S[r * n + c] = T(U)_r at cell c (n = nx ny nz) for the state (Y, T).  Device pointers;
+ * EINVAL for a bad grid or null pointers. */
+int rok4e_transport(const rok4e_grid* g, int32_t n_species, const double* Y, const double* T, double* S,
+                    void* stream);
+
+/* Device workspace bytes rok4e_split_step needs: six [ns + 1][n] FP64 arrays. */
+size_t rok4e_split_workspace_bytes(const rok4e_grid* g, int32_t n_species);
+
+/* One splitting step of size h for u' = T(u) + R(u) + src on the grid, in place in (Y, T):
+ *   SIMPLER: c_n = -T(U_n); the reaction substep u' = R(u) + src - c_n over h (the batched
+ *            ROK4E integration of the handle, forcing src - c_n); then the transport
+ *            substep u' = T(u) + c_n over h / 2 (the balanced form's first transport half
+ *            step is at rest and is skipped).  A steady state of T + R + src is kept.
+ *   STRANG:  transport u' = T(u) over h / 2, reaction u' = R(u) + src over h, transport
+ *            over h / 2.
+ * Transport substeps use nsub >= 1 classical fourth-order Runge-Kutta steps.  src is an
+ * optional cell-local constant source [(ns + 1) * n] (NULL: none), p the pressure per
+ * cell.  work: device buffer of at least rok4e_split_workspace_bytes bytes, owned by the
+ * caller.  Per-cell counts and status of the reaction substep as for rok4e_integrate. */
+int rok4e_split_step(rok4e_mech* mech, const rok4e_grid* g, int32_t scheme, double* Y, double* T,
+                     const double* p, const double* src, double h, double rtol, double atol, int32_t nsub,
+                     void* work, size_t work_bytes, void* stream);
 
 /* Evaluates the reactor right-hand side f(u) for every cell (Sec. 4.4, e:cv_reactor):
  * dY[k * n_cells + c], dT[c].  Inputs are not modified. */

@@ -62,3 +62,56 @@ def strang_step(T, R, u, h, reaction=rok4e, transport=rk4):
     u1 = transport(T, u, 0.5 * h)
     u2 = reaction(R, u1, h)
     return transport(T, u2, 0.5 * h)
+
+
+# ---- grid form: the reaction substep per cell, the model transport operator on a grid ----
+
+def transport_grid(U, nx, ny, nz, dx, vel, diff):
+    """The model transport operator on a periodic nx x ny x nz grid (cell c = x + nx (y +
+    ny z)): advection with velocity vel along x and isotropic diffusion, second-order
+    central differences, for every row of U [N, n]."""
+    N = U.shape[0]
+    V = U.reshape(N, nz, ny, nx)
+    xp, xm = np.roll(V, -1, axis=3), np.roll(V, 1, axis=3)
+    yp, ym = np.roll(V, -1, axis=2), np.roll(V, 1, axis=2)
+    zp, zm = np.roll(V, -1, axis=1), np.roll(V, 1, axis=1)
+    adv = -vel * (xp - xm) / (2.0 * dx)
+    dif = diff * (xm + xp + ym + yp + zm + zp - 6.0 * V) / (dx * dx)
+    return (adv + dif).reshape(N, -1)
+
+
+def _rows(Y, T):
+    return np.vstack([np.asarray(Y, np.float64), np.asarray(T, np.float64)[None, :]])
+
+
+def _transport_substep(U, grid, h, nsub, s0=None):
+    """u' = T(u) - s0 over h with nsub classical Runge-Kutta steps (s0 = None: 0)."""
+    N, n = U.shape
+
+    def f(v):
+        t = transport_grid(v.reshape(N, n), *grid)
+        return (t if s0 is None else t - s0).reshape(-1)
+
+    return rk4(f, U.reshape(-1), h, nsub).reshape(N, n)
+
+
+def simpler_step_grid(mech, Y, T, p, grid, h, rtol, atol, M, src=None, nsub=1, **kw):
+    """One Simpler balanced splitting step on the grid (e:simpler_balanced): c_n = -T(U_n);
+    the reaction substep u' = R(u) + src - c_n over h, cell by cell with the oracle's
+    ROK4E; the transport substep u' = T(u) + c_n over h/2.  grid = (nx, ny, nz, dx, vel,
+    diff).  Returns (Y, T, accepted, rejected, status)."""
+    U = _rows(Y, T)
+    s0 = transport_grid(U, *grid)
+    F = s0 if src is None else s0 + src
+    Yr, Tr, acc, rej, st = O.integrate(mech, U[:-1], U[-1], p, h, rtol, atol, M, S=F, **kw)
+    U2 = _transport_substep(_rows(Yr, Tr), grid, 0.5 * h, nsub, s0)
+    return U2[:-1], U2[-1], acc, rej, st
+
+
+def strang_step_grid(mech, Y, T, p, grid, h, rtol, atol, M, src=None, nsub=1, **kw):
+    """Strang splitting on the grid (e:strang_t1..e:strang_t3): transport over h/2,
+    reaction u' = R(u) + src over h, transport over h/2."""
+    U1 = _transport_substep(_rows(Y, T), grid, 0.5 * h, nsub)
+    Yr, Tr, acc, rej, st = O.integrate(mech, U1[:-1], U1[-1], p, h, rtol, atol, M, S=src, **kw)
+    U2 = _transport_substep(_rows(Yr, Tr), grid, 0.5 * h, nsub)
+    return U2[:-1], U2[-1], acc, rej, st

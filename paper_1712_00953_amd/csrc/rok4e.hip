@@ -13,6 +13,7 @@
 #include "rok4e.h"
 #include "rok4e_integrator.hpp"
 #include "rok4e_placement.hpp"
+#include "rok4e_split.hpp"
 
 namespace rok4e {
 
@@ -807,6 +808,105 @@ int rok4e_arnoldi(int64_t n_cells, rok4e_mech* m, const double* Y, const double*
                      Meff);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? ROK4E_OK : hip_fail(e);
+}
+
+size_t rok4e_split_workspace_bytes(const rok4e_grid* g, int32_t n_species) {
+  if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1 || n_species < 1) return 0;
+  const size_t n = (size_t)g->nx * g->ny * g->nz;
+  return 6 * (size_t)(n_species + 1) * n * sizeof(double);
+}
+
+}  // extern "C"
+
+namespace {
+
+bool grid_ok(const rok4e_grid* g) {
+  if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
+  if ((int64_t)g->nx * g->ny * g->nz > INT32_MAX - 1) return false;
+  return g->dx > 0.0 && std::isfinite(g->dx) && std::isfinite(g->vel) && g->diff >= 0.0 &&
+         std::isfinite(g->diff);
+}
+
+GridDev grid_dev(const rok4e_grid* g) {
+  return GridDev{g->nx, g->ny, g->nz, 0.5 / g->dx, 1.0 / (g->dx * g->dx), g->vel, g->diff};
+}
+
+int elementwise_grid(int64_t total) { return (int)std::min<int64_t>((total + 255) / 256, 65536); }
+
+// h_total of u' = T(u) - s0 (s0 may be null) in nsub classical Runge-Kutta steps, in place
+// in the state rows (Y, T).  w: five [N][n] workspace arrays (base, two stage points, acc).
+int transport_rk4(const GridDev& gd, int ns, double* Y, double* T, const double* s0, double h_total, int nsub,
+                  double* w, hipStream_t st) {
+  const int64_t n = (int64_t)gd.nx * gd.ny * gd.nz;
+  const int64_t tot = n * (ns + 1);
+  double* base = w;
+  double* sa = w + tot;
+  double* sb = w + 2 * tot;
+  double* acc = w + 3 * tot;
+  const RowsC state{Y, T};
+  const RowsC rb{base, base + (int64_t)ns * n}, ra{sa, sa + (int64_t)ns * n}, rbb{sb, sb + (int64_t)ns * n};
+  const RowsW none{nullptr, nullptr}, out{Y, T};
+  const int grid = elementwise_grid(tot);
+  const double dt = h_total / nsub;
+  for (int k = 0; k < nsub; ++k) {
+    hipLaunchKernelGGL(k_copy_rows, dim3(grid), dim3(256), 0, st, n, ns, state, base);
+    hipLaunchKernelGGL(k_rk4_stage, dim3(grid), dim3(256), 0, st, gd, ns, rb, s0, rb, acc, 1, dt / 6.0, sa,
+                       0.5 * dt, none);
+    hipLaunchKernelGGL(k_rk4_stage, dim3(grid), dim3(256), 0, st, gd, ns, ra, s0, rb, acc, 0, dt / 3.0, sb,
+                       0.5 * dt, none);
+    hipLaunchKernelGGL(k_rk4_stage, dim3(grid), dim3(256), 0, st, gd, ns, rbb, s0, rb, acc, 0, dt / 3.0, sa, dt,
+                       none);
+    hipLaunchKernelGGL(k_rk4_stage, dim3(grid), dim3(256), 0, st, gd, ns, ra, s0, rb, acc, 0, dt / 6.0,
+                       (double*)nullptr, 0.0, out);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ROK4E_OK : hip_fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rok4e_transport(const rok4e_grid* g, int32_t n_species, const double* Y, const double* T, double* S,
+                    void* stream) {
+  if (!grid_ok(g) || n_species < 1 || !Y || !T || !S) return ROK4E_EINVAL;
+  const GridDev gd = grid_dev(g);
+  const int64_t tot = (int64_t)g->nx * g->ny * g->nz * (n_species + 1);
+  hipLaunchKernelGGL(k_transport, dim3(elementwise_grid(tot)), dim3(256), 0, (hipStream_t)stream, gd, n_species,
+                     RowsC{Y, T}, S, (const double*)nullptr, (double*)nullptr);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ROK4E_OK : hip_fail(e);
+}
+
+int rok4e_split_step(rok4e_mech* m, const rok4e_grid* g, int32_t scheme, double* Y, double* T, const double* p,
+                     const double* src, double h, double rtol, double atol, int32_t nsub, void* work,
+                     size_t work_bytes, void* stream) {
+  if (!m || !grid_ok(g) || !Y || !T || !p || !work) return ROK4E_EINVAL;
+  if (scheme != ROK4E_SPLIT_SIMPLER && scheme != ROK4E_SPLIT_STRANG) return ROK4E_EINVAL;
+  if (!(h > 0.0) || !std::isfinite(h) || nsub < 1) return ROK4E_EINVAL;
+  if (work_bytes < rok4e_split_workspace_bytes(g, m->ns)) return ROK4E_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int ns = m->ns;
+  const int64_t n = (int64_t)g->nx * g->ny * g->nz;
+  const int64_t tot = n * (ns + 1);
+  const GridDev gd = grid_dev(g);
+  double* s0 = (double*)work;     // T(U_n)
+  double* f = s0 + tot;           // forcing of the reaction substep
+  double* w = f + tot;            // transport workspace (4 arrays)
+  int rc;
+  if (scheme == ROK4E_SPLIT_SIMPLER) {
+    // c_n = -T(U_n); reaction u' = R(u) + src - c_n over h; transport u' = T(u) + c_n over h/2
+    hipLaunchKernelGGL(k_transport, dim3(elementwise_grid(tot)), dim3(256), 0, st, gd, ns, RowsC{Y, T}, s0, src, f);
+    rc = rok4e_integrate_forced(n, m, Y, T, p, f, h, rtol, atol, stream);
+    if (rc) return rc;
+    return transport_rk4(gd, ns, Y, T, s0, 0.5 * h, nsub, w, st);
+  }
+  // Strang: transport h/2, reaction h, transport h/2
+  rc = transport_rk4(gd, ns, Y, T, nullptr, 0.5 * h, nsub, w, st);
+  if (rc) return rc;
+  rc = rok4e_integrate_forced(n, m, Y, T, p, src, h, rtol, atol, stream);
+  if (rc) return rc;
+  return transport_rk4(gd, ns, Y, T, nullptr, 0.5 * h, nsub, w, st);
 }
 
 int rok4e_cell_stats_ptr(rok4e_mech* m, const int32_t** acc, const int32_t** rej, const int32_t** status) {

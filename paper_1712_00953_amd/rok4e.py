@@ -20,11 +20,13 @@ LIB_PATH = os.environ.get("ROK4E_LIB") or os.path.join(HERE, "librok4e.so")
 OK, EINVAL, ENOMEM, EHIP, ECAPTURE, ENOTSUP = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 PERSISTENT, PER_ATTEMPT = 0, 1
+SPLIT_SIMPLER, SPLIT_STRANG = 0, 1
 CELL_OK, CELL_MAX_ATTEMPTS, CELL_STEP_UNDERFLOW, CELL_BAD_INPUT = 0, 1, 2, 3
 
 EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "rok4e_set_options",
            "rok4e_get_options", "rok4e_reserve", "rok4e_integrate", "rok4e_integrate_forced",
-           "rok4e_tune", "rok4e_rhs", "rok4e_arnoldi", "rok4e_get_stats", "rok4e_cell_stats_ptr",
+           "rok4e_tune", "rok4e_rhs", "rok4e_arnoldi", "rok4e_transport", "rok4e_split_workspace_bytes",
+           "rok4e_split_step", "rok4e_get_stats", "rok4e_cell_stats_ptr",
            "rok4e_copy_cell_stats", "rok4e_strerror"]
 
 
@@ -41,6 +43,11 @@ class Options(C.Structure):
                 ("fixed_steps", C.c_int32), ("lanes_per_cell", C.c_int32),
                 ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("scheduling", C.c_int32), ("h0", C.c_double)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dx", C.c_double),
+                ("vel", C.c_double), ("diff", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -80,12 +87,27 @@ def load():
         lib.rok4e_tune.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_float), vp]
         lib.rok4e_rhs.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
+        lib.rok4e_transport.argtypes = [C.POINTER(Grid), C.c_int32, vp, vp, vp, vp]
+        lib.rok4e_split_workspace_bytes.restype = C.c_size_t
+        lib.rok4e_split_workspace_bytes.argtypes = [C.POINTER(Grid), C.c_int32]
+        lib.rok4e_split_step.argtypes = [vp, C.POINTER(Grid), C.c_int32, vp, vp, vp, vp, dbl, dbl, dbl,
+                                         C.c_int32, vp, C.c_size_t, vp]
         lib.rok4e_arnoldi.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.rok4e_get_stats.argtypes = [vp, C.POINTER(Stats), vp]
         lib.rok4e_cell_stats_ptr.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
         lib.rok4e_copy_cell_stats.argtypes = [vp, vp, vp, vp, vp]
         _lib = lib
     return _lib
+
+
+def grid(nx, ny, nz, dx, vel, diff) -> Grid:
+    return Grid(int(nx), int(ny), int(nz), float(dx), float(vel), float(diff))
+
+
+def transport(g: Grid, n_species, Y, T, S, stream=None):
+    """rok4e_transport: S[r * n + c] = T(U)_r for the state (Y, T) on grid g."""
+    _check(load().rok4e_transport(C.byref(g), int(n_species), _ptr(Y), _ptr(T), _ptr(S), _stream(stream)),
+           "rok4e_transport")
 
 
 def strerror(code: int) -> str:
@@ -192,6 +214,19 @@ class Mech:
         n = int(T.shape[0])
         _check(load().rok4e_arnoldi(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(Q), _ptr(H), _ptr(Meff),
                                     _stream(stream)), "rok4e_arnoldi")
+
+    def split_step(self, grid: Grid, scheme, Y, T, p, h, rtol, atol, work, src=None, nsub=1, stream=None):
+        """rok4e_split_step: one Simpler (or Strang) step of size h on the grid, in place.
+        work: a device tensor of at least workspace_bytes(grid) bytes."""
+        n = int(grid.nx) * int(grid.ny) * int(grid.nz)
+        _check(load().rok4e_split_step(self._h, C.byref(grid), int(scheme), _ptr(Y), _ptr(T), _ptr(p), _ptr(src),
+                                       float(h), float(rtol), float(atol), int(nsub), _ptr(work),
+                                       int(work.numel() * work.element_size()), _stream(stream)),
+               "rok4e_split_step")
+        self.n_last = n
+
+    def workspace_bytes(self, grid: Grid) -> int:
+        return int(load().rok4e_split_workspace_bytes(C.byref(grid), self.n_species))
 
     def stats(self, stream=None) -> dict:
         s = Stats()
