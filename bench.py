@@ -10,7 +10,8 @@ Prints one JSON line: FP64 cell-integrations/s as `value`, the mixed-precision f
 and speed-up beside it, the roofline of the integration kernel (algorithmic FP64
 operations / kernel time against the FP64 vector peak), the standalone right-hand-side
 and Arnoldi kernels against the same peak, persistent vs per-attempt scheduling on the
-262,144-cell bimodal batch, and the CPU oracle timed on a bounded sample on this host.
+262,144-cell bimodal batch, one Simpler balanced splitting step on a 64^3 grid, and the
+CPU oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -190,6 +191,60 @@ def run_schedules(R, torch, synth):
     return out
 
 
+def run_splitting(R, torch, synth, nx=64, h=1e-6, reps=3):
+    """One Simpler balanced splitting step on an nx^3 periodic grid carrying the 53-species
+    flame profile along x (advection 10 m/s, diffusivity 2e-5 m^2/s, dx = 1e-4 m): the
+    whole step, and its reaction substep alone (same forcing), timed with HIP events."""
+    w = synth.workload(2, a_scale=A_SCALE, n_cells=4)
+    mech = w.mech
+    ns = mech.n_species
+    n = nx ** 3
+    st = synth.states_flame(mech, nx, nx * nx, 4500)
+    dev = torch.device("cuda:0")
+    Y0 = torch.tensor(st.Y, dtype=torch.float64, device=dev)
+    T0 = torch.tensor(st.T, dtype=torch.float64, device=dev)
+    p = torch.tensor(st.p, dtype=torch.float64, device=dev)
+    g = R.grid(nx, nx, nx, 1e-4, 10.0, 2e-5)
+    m = R.Mech(mech, M=w.M, max_attempts=200000)
+    m.reserve(n)
+    work = torch.empty(m.workspace_bytes(g) // 8, dtype=torch.float64, device=dev)
+    F = torch.empty((ns + 1) * n, dtype=torch.float64, device=dev)
+    R.transport(g, ns, Y0, T0, F)
+    stream = torch.cuda.current_stream()
+    Y, T = Y0.clone(), T0.clone()
+
+    def reset():
+        Y.copy_(Y0)
+        T.copy_(T0)
+
+    def step():
+        m.split_step(g, R.SPLIT_SIMPLER, Y, T, p, h, w.rtol, w.atol, work)
+
+    def reaction():
+        m.integrate(Y, T, p, h, w.rtol, w.atol, S=F)
+
+    out = {}
+    for name, fn in (("split_step", step), ("reaction_substep", reaction)):
+        ts = []
+        for _ in range(reps + 1):
+            reset()
+            ts += timed_events(torch, stream, fn, 1)
+        out[name + "_ms"] = float(np.median(ts[1:])) * 1e3
+    s = m.stats()
+    m.close()
+    t_split = out["split_step_ms"] * 1e-3
+    transport_s = max(t_split - out["reaction_substep_ms"] * 1e-3, 1e-12)
+    # algorithmic bytes of the transport part: T(U_n) with the forcing (3 passes over the
+    # [ns + 1][n] state) and one RK4 step (state copy 2, stages 4 + 6 + 6 + 5 passes)
+    tbytes = 8.0 * (ns + 1) * n * (3 + 23)
+    out.update({"grid": f"{nx}^3", "n_cells": n, "h": h, "scheme": "simpler", "rk4_substeps": 1,
+                "cells_per_s": n / t_split, "transport_ms": transport_s * 1e3,
+                "transport_GBps": tbytes / transport_s * 1e-9,
+                "transport_frac_hbm": tbytes / transport_s * 1e-9 / PEAK_HBM_GBS,
+                "reaction_attempts": s["accepted"] + s["rejected"]})
+    return out
+
+
 def run_cpu_baseline(w, target_s=10.0):
     """The oracle on a uniformly drawn sample of the batch, all host threads."""
     from oracle import oracle as O
@@ -251,7 +306,7 @@ def main():
     if not args.no_mixed:
         mixed = run_gpu(w, R.MIXED, args.steps, args.warmup, R, torch)
         log(f"mixed: {mixed['cells_per_s']:.4e} cells/s, {mixed['ms_per_step']:.2f} ms/step")
-    subsystems = schedules = None
+    subsystems = schedules = splitting = None
     if not args.no_extras:
         subsystems = run_subsystems(w, R, torch)
         log("subsystems: " + ", ".join(f"{k} {v['kernel_ms']:.3f} ms ({v['frac'] * 100:.1f}% of FP64 peak)"
@@ -259,6 +314,10 @@ def main():
         schedules = run_schedules(R, torch, synth)
         log(f"schedules: persistent {schedules['persistent']['ms']:.1f} ms, per-attempt "
             f"{schedules['per_attempt']['ms']:.1f} ms, bitwise equal {schedules['bitwise_equal']}")
+        splitting = run_splitting(R, torch, synth)
+        log(f"splitting: {splitting['grid']} Simpler step {splitting['split_step_ms']:.1f} ms "
+            f"(reaction {splitting['reaction_substep_ms']:.1f} ms, transport {splitting['transport_ms']:.2f} ms, "
+            f"{splitting['transport_GBps']:.0f} GB/s)")
     if args.copy_calibration:
         # write a 1 GiB buffer, evict it from the caches with a second one, then copy it:
         # the copy kernel reads 1 GiB and writes 1 GiB
@@ -320,6 +379,8 @@ def main():
         out["subsystems"] = subsystems
     if schedules is not None:
         out["schedules"] = schedules
+    if splitting is not None:
+        out["splitting"] = splitting
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
