@@ -173,6 +173,47 @@ def integrate(mech, Y, T, p, dt, rtol, atol, M, S=None, jvp=JVP_FD, fixed_steps=
     return Y, T, acc, rej, st
 
 
+def integrate_rkdp(mech, Y, T, p, dt, rtol, atol, S=None, fixed_steps=0, max_attempts=0, h0=0.0,
+                   nthreads=0, fma=False):
+    """The explicit Dormand-Prince 5(4) reference integrator on every cell over [0, dt];
+    returns (Y, T, accepted, rejected, status) as new arrays."""
+    h = MechHandle(mech)
+    Y = np.array(Y, np.float64, order="C", copy=True)
+    T = np.array(T, np.float64, copy=True)
+    p = np.ascontiguousarray(p, np.float64)
+    S = None if S is None else np.ascontiguousarray(S, np.float64)
+    n = T.shape[0]
+    acc = np.zeros(n, np.int32)
+    rej = np.zeros(n, np.int32)
+    st = np.zeros(n, np.int32)
+    o = make_opts(1, JVP_FD, fixed_steps, max_attempts, 0.0, h0)
+    lib(fma).orc_integrate_rkdp(C.byref(h.s), C.byref(o), C.c_int64(n), _p(Y), _p(T), _p(p), _p(S),
+                             C.c_double(dt), C.c_double(rtol), C.c_double(atol), _p(acc), _p(rej),
+                             _p(st), C.c_int(nthreads))
+    return Y, T, acc, rej, st
+
+
+def rkdp_linear(A, c, u, dt, rtol=1e-6, atol=1e-12, fixed_steps=0):
+    """RKDP 5(4) on u' = A u + c; returns (u, accepted, rejected, status)."""
+    A = np.ascontiguousarray(A, np.float64)
+    c = None if c is None else np.ascontiguousarray(c, np.float64)
+    u = np.array(u, np.float64, copy=True)
+    acc, rej, st = C.c_int32(), C.c_int32(), C.c_int32()
+    o = make_opts(1, JVP_EXACT, fixed_steps, 0, 0.0, 0.0)
+    lib().orc_rkdp_linear(C.c_int(A.shape[0]), _p(A), _p(c), C.byref(o), _p(u), C.c_double(dt),
+                          C.c_double(rtol), C.c_double(atol), C.byref(acc), C.byref(rej), C.byref(st))
+    return u, acc.value, rej.value, st.value
+
+
+def rkdp_coefficients() -> dict:
+    out = np.zeros(30)
+    lib().orc_rkdp_coefficients(_p(out))
+    names = ["c2", "c3", "c4", "c5", "a21", "a31", "a32", "a41", "a42", "a43", "a51", "a52", "a53", "a54",
+             "a61", "a62", "a63", "a64", "a65", "b1", "b3", "b4", "b5", "b6", "bh1", "bh3", "bh4", "bh5",
+             "bh6", "bh7"]
+    return dict(zip(names, out.tolist()))
+
+
 def integrate_linear(A, c, u, dt, rtol, atol, M, jvp=JVP_EXACT, fixed_steps=0, max_attempts=0,
                      h0=0.0, trace_cap=0):
     """ROK4E on u' = A u + c.  Returns (u, accepted, rejected, status) and, when

@@ -611,6 +611,88 @@ int row_dense(const P& prob, std::vector<double>& u, double dt, int nsteps, int 
   return 0;
 }
 
+// Explicit Dormand-Prince 5(4) Runge-Kutta pair (the paper's explicit reference
+// integrator, Sec. 5 efficiency study), from the published tableau: seven stages with the
+// last one evaluated at the new solution (first-same-as-last), the fifth-order solution
+// propagated and the fourth-order one used for the error estimate.
+namespace dp {
+constexpr double c2 = 1.0 / 5, c3 = 3.0 / 10, c4 = 4.0 / 5, c5 = 8.0 / 9;
+constexpr double a21 = 1.0 / 5;
+constexpr double a31 = 3.0 / 40, a32 = 9.0 / 40;
+constexpr double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;
+constexpr double a51 = 19372.0 / 6561, a52 = -25360.0 / 2187, a53 = 64448.0 / 6561, a54 = -212.0 / 729;
+constexpr double a61 = 9017.0 / 3168, a62 = -355.0 / 33, a63 = 46732.0 / 5247, a64 = 49.0 / 176,
+                 a65 = -5103.0 / 18656;
+constexpr double b1 = 35.0 / 384, b3 = 500.0 / 1113, b4 = 125.0 / 192, b5 = -2187.0 / 6784, b6 = 11.0 / 84;
+constexpr double bh1 = 5179.0 / 57600, bh3 = 7571.0 / 16695, bh4 = 393.0 / 640, bh5 = -92097.0 / 339200,
+                 bh6 = 187.0 / 2100, bh7 = 1.0 / 40;
+}  // namespace dp
+
+// One cell over [0, dt] with RKDP 5(4): the same error norm as ROK4E (weighted RMS of the
+// embedded difference, scale atol + rtol |u_{n+1}|), the elementary controller
+// h* = h min(5, max(0.2, 0.9 err^(-1/5))), h0 = dt, clipped last step.
+template <class P>
+Result rkdp_one(const P& prob, std::vector<double>& u, double dt, double rtol, double atol, const orc_opts& o) {
+  Result res;
+  const int n = prob.n();
+  const int max_att = o.max_attempts > 0 ? o.max_attempts : 1000000;
+  const bool fixed = o.fixed_steps > 0;
+  std::vector<double> k1(n), k2(n), k3(n), k4(n), k5(n), k6(n), k7(n), arg(n), u5(n);
+  double t = 0.0, h = fixed ? dt / o.fixed_steps : (o.h0 > 0.0 ? o.h0 : dt);
+  int attempts = 0, steps_done = 0;
+  prob.template f<double>(u.data(), k1.data());
+  while (fixed ? steps_done < o.fixed_steps : t < dt) {
+    if (attempts >= max_att) { res.status = 1; break; }
+    bool last = false;
+    if (!fixed && h >= (dt - t) * (1.0 - 1e-12)) { h = dt - t; last = true; }
+    for (int r = 0; r < n; ++r) arg[r] = u[r] + h * (dp::a21 * k1[r]);
+    prob.template f<double>(arg.data(), k2.data());
+    for (int r = 0; r < n; ++r) arg[r] = u[r] + h * (dp::a31 * k1[r] + dp::a32 * k2[r]);
+    prob.template f<double>(arg.data(), k3.data());
+    for (int r = 0; r < n; ++r) arg[r] = u[r] + h * (dp::a41 * k1[r] + dp::a42 * k2[r] + dp::a43 * k3[r]);
+    prob.template f<double>(arg.data(), k4.data());
+    for (int r = 0; r < n; ++r)
+      arg[r] = u[r] + h * (dp::a51 * k1[r] + dp::a52 * k2[r] + dp::a53 * k3[r] + dp::a54 * k4[r]);
+    prob.template f<double>(arg.data(), k5.data());
+    for (int r = 0; r < n; ++r)
+      arg[r] = u[r] + h * (dp::a61 * k1[r] + dp::a62 * k2[r] + dp::a63 * k3[r] + dp::a64 * k4[r] +
+                           dp::a65 * k5[r]);
+    prob.template f<double>(arg.data(), k6.data());
+    for (int r = 0; r < n; ++r)
+      u5[r] = u[r] + h * (dp::b1 * k1[r] + dp::b3 * k3[r] + dp::b4 * k4[r] + dp::b5 * k5[r] + dp::b6 * k6[r]);
+    prob.template f<double>(u5.data(), k7.data());
+    ++attempts;
+    if (fixed) {
+      u = u5;
+      k1 = k7;
+      ++res.accepted;
+      ++steps_done;
+      continue;
+    }
+    double ss = 0.0;
+    for (int r = 0; r < n; ++r) {
+      const double e = h * ((dp::b1 - dp::bh1) * k1[r] + (dp::b3 - dp::bh3) * k3[r] + (dp::b4 - dp::bh4) * k4[r] +
+                            (dp::b5 - dp::bh5) * k5[r] + (dp::b6 - dp::bh6) * k6[r] - dp::bh7 * k7[r]);
+      const double ratio = e / (atol + rtol * std::fabs(u5[r]));
+      ss += ratio * ratio;
+    }
+    double err = std::sqrt(ss / n);
+    if (!std::isfinite(err) || !all_finite(u5)) err = std::numeric_limits<double>::infinity();
+    const double fac = std::fmin(5.0, std::fmax(0.2, 0.9 * std::pow(std::fmax(err, 1e-10), -0.2)));
+    if (err <= 1.0) {
+      u = u5;
+      k1 = k7;
+      t = last ? dt : t + h;
+      ++res.accepted;
+    } else {
+      ++res.rejected;
+    }
+    h *= fac;
+    if (t < dt && h < 16.0 * std::numeric_limits<double>::epsilon() * dt) { res.status = 2; break; }
+  }
+  return res;
+}
+
 bool cell_input_ok(const orc_mech* m, const double* Y, const double* T, const double* p,
                    int64_t n, int64_t c) {
   for (int k = 0; k < m->n_species; ++k)
@@ -749,6 +831,60 @@ int orc_integrate_linear(int n, const double* A, const double* c, const orc_opts
   if (rej) *rej = r.rejected;
   if (status) *status = r.status;
   return 0;
+}
+
+// RKDP 5(4) on n cells over [0, dt] in place (the explicit reference integrator).
+int orc_integrate_rkdp(const orc_mech* m, const orc_opts* o, int64_t n, double* Y, double* T,
+                       const double* p, const double* S, double dt, double rtol, double atol,
+                       int32_t* acc, int32_t* rej, int32_t* status, int nthreads) {
+  const int ns = m->n_species;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  for (int64_t c = 0; c < n; ++c) {
+    Result r;
+    if (!cell_input_ok(m, Y, T, p, n, c)) {
+      r.status = 3;
+    } else {
+      std::vector<double> u(ns + 1), s;
+      for (int k = 0; k < ns; ++k) u[k] = Y[k * n + c];
+      u[ns] = T[c];
+      if (S) {
+        s.resize(ns + 1);
+        for (int k = 0; k <= ns; ++k) s[k] = S[k * n + c];
+      }
+      CellProblem prob{m, p[c], S ? s.data() : nullptr};
+      r = rkdp_one(prob, u, dt, rtol, atol, *o);
+      for (int k = 0; k < ns; ++k) Y[k * n + c] = u[k];
+      T[c] = u[ns];
+    }
+    if (acc) acc[c] = r.accepted;
+    if (rej) rej[c] = r.rejected;
+    if (status) status[c] = r.status;
+  }
+  return 0;
+}
+
+// RKDP 5(4) on the linear problem u' = A u + c (for the order pins).
+int orc_rkdp_linear(int n, const double* A, const double* c, const orc_opts* o, double* u, double dt,
+                    double rtol, double atol, int32_t* acc, int32_t* rej, int32_t* status) {
+  LinearProblem prob{n, A, c};
+  std::vector<double> uu(u, u + n);
+  Result r = rkdp_one(prob, uu, dt, rtol, atol, *o);
+  std::memcpy(u, uu.data(), n * sizeof(double));
+  if (acc) *acc = r.accepted;
+  if (rej) *rej = r.rejected;
+  if (status) *status = r.status;
+  return 0;
+}
+
+// Dormand-Prince tableau in the order c2..c5, a21, a31, a32, a41..a43, a51..a54,
+// a61..a65, b1, b3..b6, bh1, bh3..bh7 (30 values; b2 = bh2 = b7 = 0), for the pins.
+void orc_rkdp_coefficients(double* out) {
+  const double v[30] = {dp::c2,  dp::c3,  dp::c4,  dp::c5,  dp::a21, dp::a31, dp::a32, dp::a41,
+                        dp::a42, dp::a43, dp::a51, dp::a52, dp::a53, dp::a54, dp::a61, dp::a62,
+                        dp::a63, dp::a64, dp::a65, dp::b1,  dp::b3,  dp::b4,  dp::b5,  dp::b6,
+                        dp::bh1, dp::bh3, dp::bh4, dp::bh5, dp::bh6, dp::bh7};
+  std::memcpy(out, v, sizeof(v));
 }
 
 // ROK4E on a caller-supplied autonomous system u' = f(u) (finite-difference JVPs).
