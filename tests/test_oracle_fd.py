@@ -5,10 +5,13 @@ rounding envelope of the method.
   quadruple precision to ~1e-13 of its size; the literal difference of two FP64
   evaluations carries absolute noise eps |f| (relative noise up to ~1e-6 here).
 * Two builds of the same oracle that round differently (with and without fused
-  multiply-adds) disagree on the adaptive result by a fraction of the tolerance scale
-  atol + rtol |u|, not by 1e-10: the stage solves are conditioned like h gamma |lambda|
-  and the step sequence follows the error estimate, a small difference of two
-  solutions.  This envelope is the parity bar of the GPU path.
+  multiply-adds) agree on the adaptive result to ~1e-13 relative on every species above
+  1e-14 and take the same step sequence on every cell.  This holds only because the
+  Arnoldi basis stays orthonormal to rounding (Eq. e:solve_kry_jac needs V^T V = I):
+  with modified Gram-Schmidt alone the basis of a stiff cell loses orthogonality at
+  M = 8, the stage solves then differ by ~1e-7 between the two builds and a third of
+  the cells change their step count.  The twin's difference is the rounding floor the
+  GPU bar is scaled from.
 """
 import numpy as np
 import pytest
@@ -66,9 +69,9 @@ def test_rounding_envelope_is_within_tolerance(orc, cfg, n):
     b = orc.integrate(w.mech, st.Y, st.T, st.p, w.dt, w.rtol, w.atol, w.M, fma=True)
     e = normalized_error(b, a, w.rtol, w.atol)
     match = np.mean((a[2] == b[2]) & (a[3] == b[3]))
-    print(f"\n[envelope cfg{cfg}] normalized {e:.3e} count match {match:.3f}")
-    # rounding alone moves the result by a fraction of the tolerance scale ...
-    assert e <= 5.0
-    # ... and by far more than 1e-10 relative, so that is not a usable parity bar
-    rel = np.abs(a[0] - b[0]) / np.maximum(np.abs(a[0]), 1e-300)
-    assert rel[np.abs(a[0]) > 1e-6].max() > 1e-10
+    rel = np.abs(a[0] - b[0]) / np.maximum(np.abs(a[0]), 1e-14)
+    print(f"\n[envelope cfg{cfg}] normalized {e:.3e} relative {rel.max():.3e} count match {match:.3f}")
+    # the same step sequence everywhere, and a rounding-level difference in the result
+    assert match == 1.0
+    assert rel.max() <= 1e-12
+    assert e <= 1e-6
