@@ -61,6 +61,14 @@ extern "C" {
 #define ROK4E_PERSISTENT 0
 #define ROK4E_PER_ATTEMPT 1
 
+/* Integration method.  ROK4E: Algorithm a:ROK4E (the library's purpose).  RKDP45: the
+ * explicit Dormand-Prince 5(4) pair (published tableau, first-same-as-last, the same error
+ * norm, controller h* = h min(5, max(0.2, 0.9 err^(-1/5))), h0 = dt), the explicit
+ * reference integrator of the efficiency study of Sec. 5; persistent schedule only
+ * (ROK4E_ENOTSUP otherwise); M and the Krylov options are ignored. */
+#define ROK4E_METHOD_ROK4E 0
+#define ROK4E_METHOD_RKDP45 1
+
 typedef struct rok4e_mech rok4e_mech;   /* opaque handle */
 
 /* Mechanism description; host arrays, copied to the device by rok4e_mech_create. */
@@ -91,6 +99,8 @@ typedef struct {
   int32_t blocks_per_cu;  /* 0: automatic; persistent-grid blocks per compute unit
                              (bitwise neutral) */
   int32_t scheduling;     /* ROK4E_PERSISTENT or ROK4E_PER_ATTEMPT (bitwise neutral) */
+  int32_t method;         /* ROK4E_METHOD_ROK4E (default) or ROK4E_METHOD_RKDP45 */
+  int32_t reserved;       /* 0 */
   double h0;              /* first trial step; <= 0 means dt */
 } rok4e_options;
 

@@ -60,6 +60,32 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m,
   }
 }
 
+// Explicit Dormand-Prince 5(4) reference integrator over the same persistent queue.
+template <int L, int ROWS, class RT>
+__global__ void __launch_bounds__(256, occupancy<ROWS>()) k_rkdp(DevMech m, Launch P) {
+  extern __shared__ __align__(16) char smem[];
+  const MechLds t = load_mech_lds(m, smem);
+  const int lane = (int)(threadIdx.x % L);
+  char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
+  const SegLds<RT> S = seg_lds<RT>(seg, P);
+  init_seg<RT>(m, S);
+  while (true) {
+    const unsigned int ticket = atomicAdd(P.queue, lane == 0 ? 1u : 0u);
+    const int cell = seg_bcast<L>((int)ticket, 0);
+    if (cell < 0 || (int64_t)cell >= P.n_cells) break;
+    double u[ROWS], s[ROWS], p;
+    CellState c{};
+    c.status = 3;
+    if (load_cell<L, ROWS>(m, P, cell, lane, u, s, p)) {
+      c = rkdp_cell<L, ROWS, RT>(m, t, P, u, p, s, S, lane);
+      store_cell<L, ROWS>(m, P, cell, lane, u);
+    }
+    P.acc[cell] = c.accepted;
+    P.rej[cell] = c.rejected;
+    P.status[cell] = c.status;
+  }
+}
+
 // Device buffers of the per-attempt schedule: the state each active cell carries from
 // one launch to the next (cell-major, so a segment's lanes read contiguous rows).
 struct AttemptWork {
@@ -221,13 +247,15 @@ using ArnoldiFn = void (*)(DevMech, Launch, double*, double*, int32_t*);
 struct Variant {
   int L, rows, mmax, prec;
   IntegrateFn integrate;
+  IntegrateFn rkdp;
   AttemptFn attempt;
   ArnoldiFn arnoldi;
   RhsFn rhs;
 };
 
 #define ROK4E_VARIANT(Lv, Rv, Mv, T, P)                                                       \
-  Variant{Lv, Rv, Mv, P, k_integrate<Lv, Rv, Mv, T>, k_attempt<Lv, Rv, Mv, T>, k_arnoldi<Lv, Rv, Mv, T>, \
+  Variant{Lv, Rv, Mv, P, k_integrate<Lv, Rv, Mv, T>, k_rkdp<Lv, Rv, T>, k_attempt<Lv, Rv, Mv, T>,         \
+          k_arnoldi<Lv, Rv, Mv, T>,                                                             \
           k_rhs<Lv, Rv, T>}
 
 static const Variant kVariants[] = {
@@ -296,6 +324,7 @@ bool options_ok(const rok4e_options& o) {
   if (o.waves_per_block < 0 || o.waves_per_block > 4) return false;
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return false;
   if (o.scheduling != ROK4E_PERSISTENT && o.scheduling != ROK4E_PER_ATTEMPT) return false;
+  if (o.method != ROK4E_METHOD_ROK4E && o.method != ROK4E_METHOD_RKDP45) return false;
   if (!std::isfinite(o.h0)) return false;
   return true;
 }
@@ -701,6 +730,17 @@ int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
   P.rtol = rtol;
   P.atol = atol;
   LaunchShape sh;
+  if (m->opt.method == ROK4E_METHOD_RKDP45) {
+    if (m->opt.scheduling != ROK4E_PERSISTENT) return ROK4E_ENOTSUP;
+    rc = shape_for(m, sl, n_cells, (const void*)m->var->rkdp, true, &sh);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
+    hipLaunchKernelGGL(m->var->rkdp, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e);
+    m->last_n = n_cells;
+    return ROK4E_OK;
+  }
   if (m->opt.scheduling == ROK4E_PER_ATTEMPT) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)

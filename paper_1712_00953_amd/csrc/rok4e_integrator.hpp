@@ -47,7 +47,8 @@ __device__ __forceinline__ void rhs_forced(const DevMech& m, const MechLds& t, c
   for (int i = 0; i < ROWS; ++i) f[i] = f[i] + s[i];
 }
 
-// Arnoldi process with modified Gram-Schmidt (Sec. 4.1, e:jac_proj) on finite-difference
+// Arnoldi process with modified Gram-Schmidt and one classical re-orthogonalisation pass
+// (Sec. 4.1, e:jac_proj) on finite-difference
 // Jacobian-vector products (Sec. 4.3), J v = (f(u + delta v) - f(u)) / delta with the
 // numerator in difference form.  Q holds this lane's rows of the orthonormal basis, H
 // (LDS) the M x M Hessenberg matrix; both FP64.  Returns M_eff.  Needs the base
@@ -84,18 +85,45 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
     rhs_diff<L, ROWS, RT>(m, t, B, w, u, du, d, S.r, lane);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) wv[i] = d[i] * rdelta;
-    double hsq = 0.0;
+    double hj[MMAX];
 #pragma unroll
     for (int i2 = 0; i2 < MMAX; ++i2) {
-      if (i2 > j) break;
+      hj[i2] = 0.0;
+      if (i2 > j) continue;
       double pr[ROWS];
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) pr[i] = Q[i][i2] * wv[i];
       const double hij = seg_sum<L, ROWS>(pr);
-      S.H[i2 * MMAX + j] = hij;
-      hsq = hsq + hij * hij;
+      hj[i2] = hij;
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) wv[i] = wv[i] - hij * Q[i][i2];
+    }
+    // One classical re-orthogonalisation pass: all projections of the once-orthogonalised
+    // w at once (one batched reduction; the columns not built yet are zero), removed and
+    // added to H.  The Woodbury form of the stage solve (e:solve_kry_jac) holds for an
+    // orthonormal basis, which plain modified Gram-Schmidt does not keep on stiff cells.
+    double cpr[MMAX];
+    constexpr int KG = MMAX % 8 == 0 ? 8 : 4;
+#pragma unroll
+    for (int g = 0; g < MMAX; g += KG) {
+      double pr[ROWS][KG], cg[KG];
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i)
+#pragma unroll
+        for (int k = 0; k < KG; ++k) pr[i][k] = Q[i][g + k] * wv[i];
+      seg_sum_rows_k<L, ROWS, KG>(pr, cg);
+#pragma unroll
+      for (int k = 0; k < KG; ++k) cpr[g + k] = cg[k];
+    }
+    double hsq = 0.0;
+#pragma unroll
+    for (int i2 = 0; i2 < MMAX; ++i2) {
+      if (i2 > j) continue;
+      const double hfin = hj[i2] + cpr[i2];
+      S.H[i2 * MMAX + j] = hfin;
+      hsq = hsq + hfin * hfin;
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) wv[i] = wv[i] - cpr[i2] * Q[i][i2];
     }
     if (j + 1 < Meff) {
 #pragma unroll
@@ -385,6 +413,110 @@ __device__ __forceinline__ CellState integrate_cell(const DevMech& m, const Mech
   cell_start(P, c);
   double fn[ROWS], Q[ROWS][MMAX];
   while (cell_running(P, c)) cell_attempt<L, ROWS, MMAX, RT>(m, tab, P, u, p, s, S, lane, c, fn, Q);
+  return c;
+}
+
+// Explicit Dormand-Prince 5(4) pair (the explicit reference integrator of the efficiency
+// study, Sec. 5): published tableau, first-same-as-last, the ROK4E error norm, elementary
+// controller h* = h min(5, max(0.2, 0.9 err^(-1/5))), h0 = dt, clipped last step.
+namespace dp {
+constexpr double a21 = 1.0 / 5;
+constexpr double a31 = 3.0 / 40, a32 = 9.0 / 40;
+constexpr double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;
+constexpr double a51 = 19372.0 / 6561, a52 = -25360.0 / 2187, a53 = 64448.0 / 6561, a54 = -212.0 / 729;
+constexpr double a61 = 9017.0 / 3168, a62 = -355.0 / 33, a63 = 46732.0 / 5247, a64 = 49.0 / 176,
+                 a65 = -5103.0 / 18656;
+constexpr double b1 = 35.0 / 384, b3 = 500.0 / 1113, b4 = 125.0 / 192, b5 = -2187.0 / 6784, b6 = 11.0 / 84;
+// b - b_hat (b2 = bh2 = b7 = 0)
+constexpr double e1 = b1 - 5179.0 / 57600, e3 = b3 - 7571.0 / 16695, e4 = b4 - 393.0 / 640,
+                 e5 = b5 - (-92097.0 / 339200), e6 = b6 - 187.0 / 2100, e7 = -1.0 / 40;
+}  // namespace dp
+
+template <int L, int ROWS, class RT>
+__device__ __forceinline__ CellState rkdp_cell(const DevMech& m, const MechLds& tab, const Launch& P,
+                                               double (&u)[ROWS], double p, const double (&s)[ROWS],
+                                               const SegLds<RT>& S, int lane) {
+  const int N = m.ns + 1;
+  const double dt = P.dt;
+  const double tiny = 16.0 * 2.220446049250313e-16 * dt;
+  const bool fixed = P.fixed_steps > 0;
+  CellState c;
+  cell_start(P, c);
+  double k1[ROWS], k2[ROWS], k3[ROWS], k4[ROWS], k5[ROWS], k6[ROWS], k7[ROWS], arg[ROWS];
+  RT wt[ROWS];
+  rhs_forced<L, ROWS, RT, false>(m, tab, u, p, s, k1, S, lane, nullptr, wt);
+  while (cell_running(P, c)) {
+    double h = c.h;
+    bool last = false;
+    if (!fixed && h >= (dt - c.t) * (1.0 - 1e-12)) {
+      h = dt - c.t;
+      last = true;
+    }
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (dp::a21 * k1[i]);
+    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, k2, S, lane, nullptr, wt);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (dp::a31 * k1[i] + dp::a32 * k2[i]);
+    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, k3, S, lane, nullptr, wt);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (dp::a41 * k1[i] + dp::a42 * k2[i] + dp::a43 * k3[i]);
+    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, k4, S, lane, nullptr, wt);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i)
+      arg[i] = u[i] + h * (dp::a51 * k1[i] + dp::a52 * k2[i] + dp::a53 * k3[i] + dp::a54 * k4[i]);
+    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, k5, S, lane, nullptr, wt);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i)
+      arg[i] = u[i] + h * (dp::a61 * k1[i] + dp::a62 * k2[i] + dp::a63 * k3[i] + dp::a64 * k4[i] +
+                           dp::a65 * k5[i]);
+    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, k6, S, lane, nullptr, wt);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i)
+      arg[i] = u[i] + h * (dp::b1 * k1[i] + dp::b3 * k3[i] + dp::b4 * k4[i] + dp::b5 * k5[i] + dp::b6 * k6[i]);
+    rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, k7, S, lane, nullptr, wt);
+    ++c.attempts;
+    if (fixed) {
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        u[i] = arg[i];
+        k1[i] = k7[i];
+      }
+      ++c.accepted;
+      ++c.steps_done;
+      continue;
+    }
+    double en[ROWS][2], sums[2];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      const int r = (int)(i * L + lane);
+      en[i][0] = 0.0;
+      en[i][1] = 0.0;
+      if (r < N) {
+        const double e = h * (dp::e1 * k1[i] + dp::e3 * k3[i] + dp::e4 * k4[i] + dp::e5 * k5[i] +
+                              dp::e6 * k6[i] + dp::e7 * k7[i]);
+        const double ratio = e * rcp(P.atol + P.rtol * fabs(arg[i]));
+        en[i][0] = ratio * ratio;
+        en[i][1] = finite_(arg[i]) ? 0.0 : 1.0;
+      }
+    }
+    seg_sum_rows_k<L, ROWS, 2>(en, sums);
+    double err = sqrt(sums[0] * (1.0 / N));
+    if (!finite_(err) || sums[1] != 0.0) err = __builtin_huge_val();
+    const double fac = fmin(5.0, fmax(0.2, 0.9 * exp(-0.2 * log(fmax(err, 1e-10)))));
+    if (err <= 1.0) {
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        u[i] = arg[i];
+        k1[i] = k7[i];
+      }
+      c.t = last ? dt : c.t + h;
+      ++c.accepted;
+    } else {
+      ++c.rejected;
+    }
+    c.h = h * fac;
+    if (c.t < dt && c.h < tiny) c.status = 2;
+  }
   return c;
 }
 

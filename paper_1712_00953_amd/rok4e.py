@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EHIP, ECAPTURE, ENOTSUP = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 PERSISTENT, PER_ATTEMPT = 0, 1
 SPLIT_SIMPLER, SPLIT_STRANG = 0, 1
+METHOD_ROK4E, METHOD_RKDP45 = 0, 1
 CELL_OK, CELL_MAX_ATTEMPTS, CELL_STEP_UNDERFLOW, CELL_BAD_INPUT = 0, 1, 2, 3
 
 EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "rok4e_set_options",
@@ -42,7 +43,8 @@ class Options(C.Structure):
     _fields_ = [("M", C.c_int32), ("precision", C.c_int32), ("max_attempts", C.c_int32),
                 ("fixed_steps", C.c_int32), ("lanes_per_cell", C.c_int32),
                 ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("scheduling", C.c_int32), ("h0", C.c_double)]
+                ("scheduling", C.c_int32), ("method", C.c_int32), ("reserved", C.c_int32),
+                ("h0", C.c_double)]
 
 
 class Grid(C.Structure):
@@ -120,9 +122,10 @@ def _check(rc, what):
 
 
 def options(M=4, precision=FP64, max_attempts=0, fixed_steps=0, lanes_per_cell=0,
-            waves_per_block=0, blocks_per_cu=0, scheduling=PERSISTENT, h0=0.0) -> Options:
+            waves_per_block=0, blocks_per_cu=0, scheduling=PERSISTENT, method=METHOD_ROK4E,
+            h0=0.0) -> Options:
     return Options(int(M), int(precision), int(max_attempts), int(fixed_steps), int(lanes_per_cell),
-                   int(waves_per_block), int(blocks_per_cu), int(scheduling), float(h0))
+                   int(waves_per_block), int(blocks_per_cu), int(scheduling), int(method), 0, float(h0))
 
 
 def _ptr(t):

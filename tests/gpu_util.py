@@ -58,11 +58,21 @@ def normalized(a, b, rtol, atol):
     return float(per_cell.max()), float(np.percentile(per_cell, 99))
 
 
+def relative(gpu, orc, floor=1e-14):
+    """Largest relative error over Y (entries with max(|Y_orc|, |Y_gpu|) >= floor) and T,
+    on every cell (the tolerance metric of the FP64 and mixed bars)."""
+    Yg, Tg = gpu[0], gpu[1]
+    Yo, To = orc[0], orc[1]
+    graded = np.maximum(np.abs(Yo), np.abs(Yg)) >= floor
+    relY = np.abs(Yg - Yo)[graded] / np.abs(Yo)[graded] if graded.any() else np.zeros(1)
+    return float(max(relY.max(), (np.abs(Tg - To) / np.abs(To)).max()))
+
+
 def envelope(orc, w, st, dt, rtol, atol, **kw):
     """Oracle result and the rounding envelope: how far the FMA-contracted build of the
-    same oracle lands from it (normalized max / p99, count-match fraction)."""
+    same oracle lands from it (normalized max / p99, relative max, count-match fraction)."""
     a = orc.integrate(w.mech, st.Y, st.T, st.p, dt, rtol, atol, w.M, **kw)
     b = orc.integrate(w.mech, st.Y, st.T, st.p, dt, rtol, atol, w.M, fma=True, **kw)
     mx, p99 = normalized(b, a, rtol, atol)
     match = float(np.mean((a[2] == b[2]) & (a[3] == b[3])))
-    return a, dict(env_max=mx, env_p99=p99, env_match=match)
+    return a, dict(env_max=mx, env_p99=p99, env_rel=relative(b, a), env_match=match)

@@ -1,24 +1,26 @@
 """GPU parity of the HIP reaction substep against the FP64 oracle, through the C ABI.
 
-Tolerances (derived from the arithmetic):
+Bars:
 * right-hand side: the same formula in FP64 with different reduction trees and fused
   multiply-adds: components agree to a few ulps of the largest term they are built
   from (1e-12 relative, floor 1e-1 of the cell's largest species rate);
 * first Jacobian-vector product (Hessenberg column 0): 1e-11 of |J q_0|;
-* integration: the stage solves are conditioned like h gamma |lambda| and the step
-  sequence follows the embedded error estimate, so rounding alone moves a correct
-  result by a fraction of the tolerance scale atol + rtol |u| (measured by an
-  FMA-contracted twin build of the oracle on the same cells: the "envelope").  The FP64
-  GPU result must lie within 4x that envelope (plus 0.05) in the normalized error
-  |gpu - oracle| / (atol + rtol |oracle|), with a count-match rate within three binomial
-  standard deviations (+0.02) of the twin's on the same sample;
-* mixed FP32/FP64: normalized error <= max(10, 4x envelope) against the FP64 oracle,
-  i.e. 1e-5 relative (10 rtol) on species above atol/rtol.
+* FP64 integration: relative error at most 1e-10 on every species above 1e-14 and on T,
+  on every cell, or 4x the relative distance between the oracle and its FMA-contracted
+  twin build where that is larger (the 111-species workload, whose smallest graded
+  species sit at the rounding limit: the twin differs by ~9e-11 there); the
+  tolerance-normalised difference |gpu - oracle| / (atol + rtol |oracle|) within 4x the
+  twin's (+1e-6); the accept/reject counts match on all but a binomial-noise fraction of
+  the cells the twin matches;
+* mixed FP32/FP64 at rtol = 1e-6: relative error at most 1e-5 on every species above 1e-14
+  (9- and 53-species workloads); 1e-4 on the 111-species workload, where FP32 rate
+  constants of near-equilibrium reactions lose relative accuracy in the forward/reverse
+  cancellation.
 """
 import numpy as np
 import pytest
 
-from gpu_util import dev_state, envelope, gpu_integrate, normalized, parity, parity_all
+from gpu_util import dev_state, envelope, gpu_integrate, normalized, parity, parity_all, relative
 from paper_1712_00953_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -114,7 +116,8 @@ def test_fixed_step_parity(R, orc, cfg):
     mx, p99 = normalized(g, o, w.rtol, w.atol)
     d = dict(norm_max=mx, norm_p99=p99, **env, **parity_all(g, o))
     _report(f"fixed cfg{cfg}", d)
-    assert mx <= 4 * env["env_max"] + 0.05
+    assert mx <= 4 * env["env_max"] + 1e-6
+    assert relative(g, o) <= max(1e-10, 4 * env["env_rel"])
     m.close()
 
 
@@ -128,10 +131,11 @@ def test_adaptive_parity_fp64(R, orc, cfg, n):
     o, env = envelope(orc, w, st, w.dt, w.rtol, w.atol, max_attempts=MAX_ATT)
     mx, p99 = normalized(g, o, w.rtol, w.atol)
     d = dict(norm_max=mx, norm_p99=p99, **env, **parity(g, o))
-    d.update(mean_attempts=float((o[2] + o[3]).mean()))
+    d.update(mean_attempts=float((o[2] + o[3]).mean()), rel=relative(g, o))
     _report(f"adaptive fp64 cfg{cfg}", d)
     assert np.all(g[4] == 0) and np.all(o[4] == 0)
-    assert mx <= 4 * env["env_max"] + 0.05
+    assert mx <= 4 * env["env_max"] + 1e-6
+    assert relative(g, o) <= max(1e-10, 4 * env["env_rel"])
     assert d["match_frac"] >= match_floor(env["env_match"], st.n_cells)
     m.close()
 
@@ -147,13 +151,14 @@ def test_adaptive_parity_fp64_cfg4(R, orc):
     d = dict(norm_max=mx, norm_p99=p99, **env, **parity(g, o))
     _report("adaptive fp64 cfg4", d)
     assert np.all(g[4] == 0)
-    assert mx <= 4 * env["env_max"] + 0.05
+    assert mx <= 4 * env["env_max"] + 1e-6
+    assert relative(g, o) <= max(1e-10, 4 * env["env_rel"])
     assert d["match_frac"] >= match_floor(env["env_match"], st.n_cells)
     m.close()
 
 
 @pytest.mark.parametrize("cfg,n,rtol,tol", [(1, 512, 1e-6, 1e-5), (2, 512, 1e-6, 1e-5),
-                                            (4, 128, 1e-6, 1e-5)])
+                                            (4, 128, 1e-6, 1e-4)])
 def test_mixed_parity(R, orc, cfg, n, rtol, tol):
     w = synth.workload(cfg, a_scale=A_SCALE)
     idx = synth.stratified_sample(w.states.T, n, 200 + cfg)
@@ -165,7 +170,9 @@ def test_mixed_parity(R, orc, cfg, n, rtol, tol):
     d = dict(norm_max=mx, norm_p99=p99, **env, **parity_all(g, o))
     _report(f"mixed cfg{cfg} rtol={rtol:g}", d)
     assert np.all(g[4] == 0)
-    assert mx <= max(tol / rtol, 4 * env["env_max"])
+    d.update(rel=relative(g, o))
+    _report(f"mixed cfg{cfg} relative", dict(rel=d["rel"], bar=tol))
+    assert d["rel"] <= tol
     m.close()
 
 
@@ -188,7 +195,8 @@ def test_layouts_agree_and_runs_are_deterministic(R, orc):
                 np.testing.assert_array_equal(a, b)
         mx, p99 = normalized(outs[0], o, w.rtol, w.atol)
         _report(f"layout L={L}", dict(norm_max=mx, norm_p99=p99, **env))
-        assert mx <= 4 * env["env_max"] + 0.05
+        assert mx <= 4 * env["env_max"] + 1e-6
+        assert relative(outs[0], o) <= max(1e-10, 4 * env["env_rel"])
 
 
 @pytest.mark.parametrize("cfg,n", [(1, 300), (3, 512)])
@@ -259,6 +267,29 @@ def test_tune_leaves_inputs_and_results_unchanged(R):
     after = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
     for a, b in zip(before, after):
         np.testing.assert_array_equal(a, b)
+    m.close()
+
+
+@pytest.mark.parametrize("cfg,n,dt", [(1, 512, 2e-6), (2, 256, 2e-6)])
+def test_rkdp_parity(R, orc, cfg, n, dt):
+    """The explicit Dormand-Prince reference integrator against the oracle's, with the same
+    rounding-envelope bar (its FMA twin) as ROK4E."""
+    w = synth.workload(cfg, a_scale=A_SCALE)
+    idx = synth.stratified_sample(w.states.T, n, 500 + cfg)
+    st = w.states.subset(idx)
+    m = R.Mech(w.mech, M=w.M, method=R.METHOD_RKDP45, max_attempts=MAX_ATT)
+    g = gpu_integrate(m, st, dt, w.rtol, w.atol)
+    o = orc.integrate_rkdp(w.mech, st.Y, st.T, st.p, dt, w.rtol, w.atol, max_attempts=MAX_ATT)
+    f = orc.integrate_rkdp(w.mech, st.Y, st.T, st.p, dt, w.rtol, w.atol, max_attempts=MAX_ATT, fma=True)
+    env = normalized(f, o, w.rtol, w.atol)[0]
+    env_match = float(np.mean((f[2] == o[2]) & (f[3] == o[3])))
+    mx, p99 = normalized(g, o, w.rtol, w.atol)
+    d = dict(norm_max=mx, norm_p99=p99, env_max=env, env_match=env_match, **parity(g, o))
+    d.update(mean_attempts=float((o[2] + o[3]).mean()))
+    _report(f"rkdp cfg{cfg}", d)
+    assert np.all(g[4] == 0) and np.all(o[4] == 0)
+    assert mx <= 4 * env + 0.05
+    assert d["match_frac"] >= match_floor(env_match, st.n_cells)
     m.close()
 
 
@@ -333,8 +364,10 @@ def test_full_batch_sampled(R, orc, cfg, n_check):
     d = dict(norm_max=mx, norm_p99=p99, **env, **parity(gs, o))
     # whole-batch invariants: mass fractions still sum to their initial totals
     d.update(sumY_drift=float(np.abs(g[0].sum(0) - st.Y.sum(0)).max()))
+    d.update(rel=relative(gs, o))
     _report(f"full cfg{cfg}", d)
-    assert mx <= 4 * env["env_max"] + 0.05
+    assert mx <= 4 * env["env_max"] + 1e-6
+    assert d["rel"] <= max(1e-10, 4 * env["env_rel"])
     assert d["match_frac"] >= match_floor(env["env_match"], n_check)
     assert d["sumY_drift"] <= 1e-9
     m.close()
