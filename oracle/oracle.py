@@ -205,6 +205,19 @@ def rkdp_linear(A, c, u, dt, rtol=1e-6, atol=1e-12, fixed_steps=0):
     return u, acc.value, rej.value, st.value
 
 
+def lu_solve(A, b):
+    """A^{-1} b through the oracle's LU with partial pivoting; returns (x, piv)."""
+    A = np.ascontiguousarray(A, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    m = A.shape[0]
+    x = np.zeros(m)
+    piv = np.zeros(m, np.int32)
+    rc = lib().orc_lu_solve(C.c_int(m), _p(A), _p(b), _p(x), piv.ctypes.data_as(C.POINTER(C.c_int32)))
+    if rc != 0:
+        raise ZeroDivisionError("zero pivot")
+    return x, piv
+
+
 def rkdp_coefficients() -> dict:
     out = np.zeros(30)
     lib().orc_rkdp_coefficients(_p(out))

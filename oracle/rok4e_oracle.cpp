@@ -893,6 +893,20 @@ int orc_rkdp_linear(int n, const double* A, const double* c, const orc_opts* o, 
 
 // Dormand-Prince tableau in the order c2..c5, a21, a31, a32, a41..a43, a51..a54,
 // a61..a65, b1, b3..b6, bh1, bh3..bh7 (30 values; b2 = bh2 = b7 = 0), for the pins.
+// x = A^{-1} b through lu_factor / lu_solve (the projected solve of the stages), for
+// the pins; piv (m entries, may be null) receives the row chosen at each step.
+// Returns 0, or -1 for a zero pivot.
+int orc_lu_solve(int m, const double* A, const double* b, double* x, int* piv) {
+  std::vector<double> a(A, A + (size_t)m * m);
+  std::vector<int> pv;
+  if (!lu_factor(a, m, pv)) return -1;
+  for (int i = 0; i < m; ++i) x[i] = b[i];
+  lu_solve(a, m, pv, x);
+  if (piv)
+    for (int i = 0; i < m; ++i) piv[i] = pv[i];
+  return 0;
+}
+
 void orc_rkdp_coefficients(double* out) {
   const double v[30] = {dp::c2,  dp::c3,  dp::c4,  dp::c5,  dp::a21, dp::a31, dp::a32, dp::a41,
                         dp::a42, dp::a43, dp::a51, dp::a52, dp::a53, dp::a54, dp::a61, dp::a62,

@@ -350,9 +350,9 @@ const Variant* pick_variant(int ns, const rok4e_options& o) {
 
 // Per-segment LDS: concentrations and increments [2][LP] and the rate-constant pairs
 // [NRP] in the rate type, production accumulators [LP], H, LU [MMAX^2] and 1/diag(U)
-// [MMAX] in FP64; piv [MMAX].
+// [MMAX] in FP64.
 struct SegLayout {
-  int bytes, off_k, off_H, off_LU, off_rdiag, off_piv;
+  int bytes, off_k, off_H, off_LU, off_rdiag;
 };
 
 int n_rx_padded(int nr) { return (std::max(nr, 1) + 1) & ~1; }
@@ -374,8 +374,6 @@ SegLayout seg_layout(int nr, const Variant& v) {
   off = al16(off + v.mmax * v.mmax * 8);
   s.off_rdiag = off;
   off = al16(off + v.mmax * 8);
-  s.off_piv = off;
-  off = al16(off + v.mmax * 4);
   s.bytes = off;
   return s;
 }
@@ -543,7 +541,6 @@ Launch base_launch(rok4e_mech* m, int64_t n, double* Y, double* T, const double*
   P.off_H = sl.off_H;
   P.off_LU = sl.off_LU;
   P.off_rdiag = sl.off_rdiag;
-  P.off_piv = sl.off_piv;
   return P;
 }
 

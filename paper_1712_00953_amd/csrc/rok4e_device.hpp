@@ -82,7 +82,7 @@ struct Launch {
   int M, max_attempts, fixed_steps;
   unsigned int* queue;
   int32_t* acc; int32_t* rej; int32_t* status;
-  int seg_bytes, off_k, off_H, off_LU, off_rdiag, off_piv;
+  int seg_bytes, off_k, off_H, off_LU, off_rdiag;
 };
 
 // Copies the table image to the start of the block's LDS and returns the view.  All

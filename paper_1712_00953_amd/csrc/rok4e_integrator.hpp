@@ -13,7 +13,6 @@ struct SegLds {
   double* H;      // [MMAX * MMAX] Hessenberg matrix of the Arnoldi process
   double* LU;     // [MMAX * MMAX] factors of I - h gamma H
   double* rdiag;  // [MMAX] reciprocals of the diagonal of U
-  int* piv;       // [MMAX]
 };
 
 template <class RT>
@@ -23,7 +22,6 @@ __device__ __forceinline__ SegLds<RT> seg_lds(char* seg, const Launch& P) {
   S.H = (double*)(seg + P.off_H);
   S.LU = (double*)(seg + P.off_LU);
   S.rdiag = (double*)(seg + P.off_rdiag);
-  S.piv = (int*)(seg + P.off_piv);
   return S;
 }
 
@@ -64,6 +62,12 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
   for (int i = 0; i < ROWS; ++i)
 #pragma unroll
     for (int j = 0; j < MMAX; ++j) Q[i][j] = 0.0;
+  // H is zero wherever the process does not reach (past M_eff, or all of it when
+  // f_n = 0): the Hessenberg part is cleared first (every lane stores the same zeros).
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j)
+#pragma unroll
+    for (int i = 0; i <= j + 1 && i < MMAX; ++i) S.H[i * MMAX + j] = 0.0;
   double sq[ROWS];
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) sq[i] = fn[i] * fn[i];
@@ -147,68 +151,79 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
   return Meff;
 }
 
-// LU with partial pivoting of the upper-Hessenberg I - h gamma H (rows k and k+1 are the
-// only pivot candidates of column k).  Every lane of the segment computes and writes the
-// same values, so no lane-dependent branch is needed.
+// LU with partial pivoting of the upper-Hessenberg A = I - hg H, hg = h gamma, over the
+// full MMAX x MMAX: H is zero past M_eff (the Arnoldi process clears it), so A is the
+// identity there and the padding neither pivots nor changes the leading block.  Only
+// rows k and k+1 are pivot candidates in column k.  The row interchanges are recorded
+// as bits of piv and the multipliers l_k kept at LU[(k+1) MMAX + k] without being moved
+// by later interchanges, so a solve applies interchange k and elimination k in turn
+// (the same operations on the same values as interchanging all rows first and
+// substituting with the permuted unit-lower factor).  Every lane of the segment
+// computes the same values in registers, two rows at a time: r is the pivot row k, s
+// row k + 1, nx row k + 2 loaded one step ahead.  U goes to LU (upper part), the
+// reciprocals of its diagonal to rdiag.  False when a pivot is zero.
 template <int MMAX>
-__device__ __forceinline__ bool lu_factor(double* a, double* rdiag, int* piv, int m) {
-  for (int k = 0; k < m; ++k) {
-    int pk = k;
-    if (k + 1 < m && fabs(a[(k + 1) * MMAX + k]) > fabs(a[k * MMAX + k])) pk = k + 1;
-    piv[k] = pk;
-    if (pk != k) {
-      for (int j = 0; j < m; ++j) {
-        const double x = a[k * MMAX + j], y = a[pk * MMAX + j];
-        lds_sync();
-        a[k * MMAX + j] = y;
-        a[pk * MMAX + j] = x;
+__device__ __forceinline__ bool lu_factor(const double* __restrict__ H, double hg, double* __restrict__ LU,
+                                          double* __restrict__ rdiag, unsigned& piv) {
+  double r[MMAX], nx[MMAX];
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j) r[j] = (j == 0 ? 1.0 : 0.0) - hg * H[j];
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j) nx[j] = (j == 1 ? 1.0 : 0.0) - hg * H[MMAX + j];
+  piv = 0u;
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < MMAX; ++k) {
+    double s[MMAX];
+    if (k + 1 < MMAX) {
+#pragma unroll
+      for (int j = k; j < MMAX; ++j) s[j] = nx[j];
+      if (k + 2 < MMAX) {
+#pragma unroll
+        for (int j = k + 1; j < MMAX; ++j) nx[j] = (j == k + 2 ? 1.0 : 0.0) - hg * H[(k + 2) * MMAX + j];
+      }
+      const bool pv = fabs(s[k]) > fabs(r[k]);
+      piv |= pv ? (1u << k) : 0u;
+#pragma unroll
+      for (int j = k; j < MMAX; ++j) {
+        const double a = r[j], b = s[j];
+        r[j] = pv ? b : a;
+        s[j] = pv ? a : b;
       }
     }
-    lds_sync();
-    const double akk = a[k * MMAX + k];
-    if (akk == 0.0) return false;
+    const double akk = r[k];
+    ok = ok && akk != 0.0;
     const double rk = 1.0 / akk;
     rdiag[k] = rk;
-    if (k + 1 < m) {
-      const double l = a[(k + 1) * MMAX + k] * rk;
-      for (int j = k + 1; j < m; ++j) {
-        const double v = a[(k + 1) * MMAX + j] - l * a[k * MMAX + j];
-        a[(k + 1) * MMAX + j] = v;
-      }
-      a[(k + 1) * MMAX + k] = l;
-      lds_sync();
+#pragma unroll
+    for (int j = k + 1; j < MMAX; ++j) LU[k * MMAX + j] = r[j];
+    if (k + 1 < MMAX) {
+      const double l = s[k] * rk;
+      LU[(k + 1) * MMAX + k] = l;
+#pragma unroll
+      for (int j = k + 1; j < MMAX; ++j) r[j] = s[j] - l * r[j];
     }
   }
-  return true;
+  return ok;
 }
 
-// x <- (I - h gamma H)^{-1} x for a uniform vector x (all row interchanges first).
+// x <- A^{-1} x for a segment-uniform vector x with the factors of lu_factor.
 template <int MMAX>
-__device__ __forceinline__ void lu_solve(const double* a, const double* rdiag, const int* piv, int m,
-                                         double (&x)[MMAX]) {
+__device__ __forceinline__ void lu_solve(const double* __restrict__ LU, const double* __restrict__ rdiag,
+                                         unsigned piv, double (&x)[MMAX]) {
 #pragma unroll
-  for (int k = 0; k < MMAX - 1; ++k) {
-    if (k >= m) break;
-    if (piv[k] != k) {
-      const double t = x[k];
-      x[k] = x[k + 1];
-      x[k + 1] = t;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < MMAX - 1; ++k) {
-    if (k + 1 >= m) break;
-    x[k + 1] = x[k + 1] - a[(k + 1) * MMAX + k] * x[k];
+  for (int k = 0; k + 1 < MMAX; ++k) {
+    const bool pv = ((piv >> k) & 1u) != 0u;
+    const double a = x[k], b = x[k + 1];
+    x[k] = pv ? b : a;
+    x[k + 1] = (pv ? a : b) - LU[(k + 1) * MMAX + k] * x[k];
   }
 #pragma unroll
   for (int i = MMAX - 1; i >= 0; --i) {
-    if (i < m) {
-      double sacc = x[i];
+    double sacc = x[i];
 #pragma unroll
-      for (int j = i + 1; j < MMAX; ++j)
-        if (j < m) sacc = sacc - a[i * MMAX + j] * x[j];
-      x[i] = sacc * rdiag[i];
-    }
+    for (int j = i + 1; j < MMAX; ++j) sacc = sacc - LU[i * MMAX + j] * x[j];
+    x[i] = sacc * rdiag[i];
   }
 }
 
@@ -216,8 +231,8 @@ __device__ __forceinline__ void lu_solve(const double* a, const double* rdiag, c
 // (Algorithm a:ROK4E, stage update; Woodbury form e:solve_kry_jac).
 template <int L, int ROWS, int MMAX>
 __device__ __forceinline__ void stage_solve(const double (&F)[ROWS], const double (&corr)[ROWS],
-                                            double (&k)[ROWS], const double (&Q)[ROWS][MMAX], int Meff,
-                                            const double* LU, const double* rdiag, const int* piv) {
+                                            double (&k)[ROWS], const double (&Q)[ROWS][MMAX],
+                                            const double* LU, const double* rdiag, unsigned piv) {
   // All MMAX projections are formed (columns past M_eff are zero) and reduced together,
   // in groups of up to eight.
   double z[MMAX], y[MMAX];
@@ -237,13 +252,14 @@ __device__ __forceinline__ void stage_solve(const double (&F)[ROWS], const doubl
       y[g + k] = zg[k];
     }
   }
-  if (Meff > 0) lu_solve<MMAX>(LU, rdiag, piv, Meff, y);
+  // past M_eff the columns of Q, z and y are zero, so the padded solve and sum add
+  // exact zeros
+  lu_solve<MMAX>(LU, rdiag, piv, y);
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     double qw = 0.0;
 #pragma unroll
-    for (int i2 = 0; i2 < MMAX; ++i2)
-      if (i2 < Meff) qw = qw + Q[i][i2] * (z[i2] - y[i2]);
+    for (int i2 = 0; i2 < MMAX; ++i2) qw = qw + Q[i][i2] * (z[i2] - y[i2]);
     k[i] = F[i] - qw - corr[i];
   }
 }
@@ -302,16 +318,8 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
     c.Meff = arnoldi<L, ROWS, MMAX, RT>(m, tab, P, u, fn, base, wbase, Q, S, lane);
     c.basis_valid = 1;
   }
-  const int Meff = c.Meff;
-  // L = I - h gamma H, factored once per attempt.  Only the Hessenberg part of the LDS
-  // copy of H is written by the Arnoldi process; the rest is zero.
-  for (int i = 0; i < Meff; ++i)
-    for (int j = 0; j < Meff; ++j) {
-      const double hij = i <= j + 1 ? S.H[i * MMAX + j] : 0.0;
-      S.LU[i * MMAX + j] = (i == j ? 1.0 : 0.0) - h * G * hij;
-    }
-  lds_sync();
-  if (Meff > 0 && !lu_factor<MMAX>(S.LU, S.rdiag, S.piv, Meff)) {
+  unsigned piv;
+  if (!lu_factor<MMAX>(S.H, h * G, S.LU, S.rdiag, piv)) {
     ++c.attempts;
     ++c.rejected;
     c.h = h * 0.2;
@@ -324,7 +332,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
   // Stage 1: F1 = f_n.
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) corr[i] = 0.0;
-  stage_solve<L, ROWS, MMAX>(fn, corr, k1, Q, Meff, S.LU, S.rdiag, S.piv);
+  stage_solve<L, ROWS, MMAX>(fn, corr, k1, Q, S.LU, S.rdiag, piv);
   // Stage 2: F2 = f(u + h a21 k1) + (g21/g) k1.
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A21 * k1[i]);
@@ -334,7 +342,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
     corr[i] = (G21 / G) * k1[i];
     F[i] = fs[i] + corr[i];
   }
-  stage_solve<L, ROWS, MMAX>(F, corr, k2, Q, Meff, S.LU, S.rdiag, S.piv);
+  stage_solve<L, ROWS, MMAX>(F, corr, k2, Q, S.LU, S.rdiag, piv);
   // Stage 3: F3 = f(u + h(a31 k1 + a32 k2)) + (g31 k1 + g32 k2)/g.
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A31 * k1[i] + A32 * k2[i]);
@@ -344,14 +352,14 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
     corr[i] = (G31 * k1[i] + G32 * k2[i]) * (1.0 / G);
     F[i] = fs[i] + corr[i];
   }
-  stage_solve<L, ROWS, MMAX>(F, corr, k3, Q, Meff, S.LU, S.rdiag, S.piv);
+  stage_solve<L, ROWS, MMAX>(F, corr, k3, Q, S.LU, S.rdiag, piv);
   // Stage 4 reuses f of stage 3 (a41 = a31, a42 = a32, a43 = 0).
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     corr[i] = (G41 * k1[i] + G42 * k2[i] + G43 * k3[i]) * (1.0 / G);
     F[i] = fs[i] + corr[i];
   }
-  stage_solve<L, ROWS, MMAX>(F, corr, k4, Q, Meff, S.LU, S.rdiag, S.piv);
+  stage_solve<L, ROWS, MMAX>(F, corr, k4, Q, S.LU, S.rdiag, piv);
 
   double us[ROWS];
 #pragma unroll

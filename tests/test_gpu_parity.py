@@ -8,7 +8,9 @@ Bars:
 * FP64 integration: relative error at most 1e-10 on every species above 1e-14 and on T,
   on every cell, or 4x the relative distance between the oracle and its FMA-contracted
   twin build where that is larger (the 111-species workload, whose smallest graded
-  species sit at the rounding limit: the twin differs by ~9e-11 there); the
+  species sit at the rounding limit: the twin differs by ~9e-11 there; on the stiffer
+  mechanism of the row-interchange test the envelope also covers one-ulp perturbations
+  of the input, which move the oracle's own result far more than the twin does); the
   tolerance-normalised difference |gpu - oracle| / (atol + rtol |oracle|) within 4x the
   twin's (+1e-6); the accept/reject counts match on all but a binomial-noise fraction of
   the cells the twin matches;
@@ -118,6 +120,47 @@ def test_fixed_step_parity(R, orc, cfg):
     _report(f"fixed cfg{cfg}", d)
     assert mx <= 4 * env["env_max"] + 1e-6
     assert relative(g, o) <= max(1e-10, 4 * env["env_rel"])
+    m.close()
+
+
+def _interchanging_cells(orc, w, st, h):
+    """Cells whose projected matrix I - h gamma H at the initial state interchanges rows
+    after the first elimination step."""
+    G = orc.coefficients()["gamma"]
+    out = []
+    for c in range(st.n_cells):
+        u = np.concatenate([st.Y[:, c], [st.T[c]]])
+        Q, H, me = orc.cell_arnoldi(w.mech, u, st.p[c], w.M, orc.JVP_FD)
+        _, piv = orc.lu_solve(np.eye(me) - h * G * H[:me, :me], np.ones(me))
+        if np.any(piv[1:] != np.arange(1, me)):
+            out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("fixed,dt", [(1, 1e-7), (0, 1e-6)])
+def test_projected_solve_with_row_interchanges(R, orc, fixed, dt):
+    """The stiffer mechanism (pre-exponential factors x 1e-5) at h = 1e-7 and 1e-6: the
+    projected LU interchanges rows after its first step on many cells (a solve that
+    mishandles the stored multipliers is wrong by O(1) there); one fixed step (h = 1e-7,
+    where every cell stays finite) and the adaptive run over 1e-6.  One step of 1e-7
+    from these far-from-equilibrium states is ill-conditioned (a one-ulp change of the
+    input moves the result by up to ~4e-10 relative), so the envelope includes one-ulp
+    input perturbations besides the twin build."""
+    w = synth.workload(1, a_scale=1e-5, n_cells=128)
+    st = w.states
+    piv_cells = _interchanging_cells(orc, w, st, dt)
+    assert len(piv_cells) >= 10
+    kw = dict(fixed_steps=1) if fixed else dict(max_attempts=MAX_ATT)
+    m = R.Mech(w.mech, M=w.M, **kw)
+    g = gpu_integrate(m, st, dt, w.rtol, w.atol)
+    o, env = envelope(orc, w, st, dt, w.rtol, w.atol, perturb=3, **kw)
+    mx, p99 = normalized(g, o, w.rtol, w.atol)
+    d = dict(n_interchanging=len(piv_cells), norm_max=mx, **env, **parity(g, o), rel=relative(g, o))
+    _report(f"interchanges fixed={fixed}", d)
+    assert np.all(g[4] == 0) and np.all(o[4] == 0)
+    assert mx <= 4 * env["env_max"] + 1e-6
+    assert d["rel"] <= max(1e-10, 4 * env["env_rel"])
+    assert d["match_frac"] >= match_floor(env["env_match"], st.n_cells)
     m.close()
 
 
