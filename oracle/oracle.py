@@ -154,9 +154,11 @@ def make_opts(M, jvp=JVP_FD, fixed_steps=0, max_attempts=0, eps_fd=0.0, h0=0.0):
 
 
 def integrate(mech, Y, T, p, dt, rtol, atol, M, S=None, jvp=JVP_FD, fixed_steps=0,
-              max_attempts=0, eps_fd=0.0, h0=0.0, nthreads=0, fma=False):
+              max_attempts=0, eps_fd=0.0, h0=0.0, nthreads=0, fma=False, h_io=None):
     """Integrate every cell over [0, dt]; returns (Y, T, accepted, rejected, status)
-    as new arrays (inputs untouched).  fma=True runs the FMA-contracted twin build."""
+    as new arrays (inputs untouched).  fma=True runs the FMA-contracted twin build.
+    h_io (float64 [n], updated in place): per-cell first trial steps (<= 0: h0 or dt),
+    replaced by the step to start the next call from."""
     h = MechHandle(mech)
     Y = np.array(Y, np.float64, order="C", copy=True)
     T = np.array(T, np.float64, copy=True)
@@ -167,9 +169,15 @@ def integrate(mech, Y, T, p, dt, rtol, atol, M, S=None, jvp=JVP_FD, fixed_steps=
     rej = np.zeros(n, np.int32)
     st = np.zeros(n, np.int32)
     o = make_opts(M, jvp, fixed_steps, max_attempts, eps_fd, h0)
-    lib(fma).orc_integrate(C.byref(h.s), C.byref(o), C.c_int64(n), _p(Y), _p(T), _p(p), _p(S),
-                        C.c_double(dt), C.c_double(rtol), C.c_double(atol), _p(acc), _p(rej),
-                        _p(st), C.c_int(nthreads))
+    if h_io is None:
+        lib(fma).orc_integrate(C.byref(h.s), C.byref(o), C.c_int64(n), _p(Y), _p(T), _p(p), _p(S),
+                               C.c_double(dt), C.c_double(rtol), C.c_double(atol), _p(acc), _p(rej),
+                               _p(st), C.c_int(nthreads))
+    else:
+        assert h_io.dtype == np.float64 and h_io.shape == (n,) and h_io.flags.c_contiguous
+        lib(fma).orc_integrate_h(C.byref(h.s), C.byref(o), C.c_int64(n), _p(Y), _p(T), _p(p), _p(S),
+                                 C.c_double(dt), C.c_double(rtol), C.c_double(atol), _p(h_io), _p(acc),
+                                 _p(rej), _p(st), C.c_int(nthreads))
     return Y, T, acc, rej, st
 
 

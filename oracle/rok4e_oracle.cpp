@@ -430,6 +430,7 @@ struct Result {
   int status = 0;       // 0 ok, 1 attempt limit, 2 step underflow, 3 bad input, 4 bad mode
   int accepted = 0;
   int rejected = 0;
+  double h_next = 0.0;  // first trial step for a following call (see rok4e_one)
 };
 
 // Optional per-attempt record: (t at the start of the attempt, h, err, accepted).
@@ -454,8 +455,12 @@ bool all_finite(const std::vector<double>& x) {
 // One cell: Algorithm a:ROK4E over [0, dt].  u is overwritten with the state at dt
 // (or at the last accepted time on failure).
 template <class P>
+// h0_cell > 0 (finite) replaces the first trial step h_0 of Algorithm a:ROK4E for this
+// call.  res.h_next is the step to start a following call from: the controller's
+// proposal after the last attempt, or, when the last accepted step had been shortened
+// to end at dt, the larger of that proposal and the one made before the shortening.
 Result rok4e_one(const P& prob, std::vector<double>& u, double dt, double rtol, double atol,
-                 const orc_opts& o, Trace* trace = nullptr) {
+                 const orc_opts& o, Trace* trace = nullptr, double h0_cell = 0.0) {
   Result res;
   const int n = prob.n();
   const int M = o.M;
@@ -470,11 +475,13 @@ Result rok4e_one(const P& prob, std::vector<double>& u, double dt, double rtol, 
 
   double t = 0.0;
   double h = o.h0 > 0.0 ? o.h0 : dt;
+  if (h0_cell > 0.0 && std::isfinite(h0_cell)) h = h0_cell;
   double err_prev = 1.0;
   int attempts = 0;
   const bool fixed = o.fixed_steps > 0;
   if (fixed) h = dt / o.fixed_steps;
   int steps_done = 0;
+  res.h_next = h;
 
   // Applies k = F - Q (z - y) - sum_j (gamma_ij / gamma) k_j with y = (I - h gamma H)^{-1} z,
   // z = Q^T F (Algorithm a:ROK4E, stage update).
@@ -493,6 +500,7 @@ Result rok4e_one(const P& prob, std::vector<double>& u, double dt, double rtol, 
   std::vector<double> corr(n);
   while (fixed ? steps_done < o.fixed_steps : t < dt) {
     if (attempts >= max_att) { res.status = 1; break; }
+    const double hprop = h;   // the controller's proposal, before any shortening
     bool last = false;
     if (!fixed && h >= (dt - t) * (1.0 - 1e-12)) { h = dt - t; last = true; }
 
@@ -511,6 +519,7 @@ Result rok4e_one(const P& prob, std::vector<double>& u, double dt, double rtol, 
       // Singular projected matrix: treat as a failed (rejected) attempt.
       ++attempts; ++res.rejected;
       h *= 0.2;
+      res.h_next = h;
       if (h < 16.0 * std::numeric_limits<double>::epsilon() * dt) { res.status = 2; break; }
       continue;
     }
@@ -566,9 +575,11 @@ Result rok4e_one(const P& prob, std::vector<double>& u, double dt, double rtol, 
       h = hstar;
       ++res.accepted;
       basis_valid = false;
+      res.h_next = last ? std::fmax(hstar, hprop) : hstar;
     } else {
       h = hstar;
       ++res.rejected;
+      res.h_next = hstar;
     }
     if (t < dt && h < 16.0 * std::numeric_limits<double>::epsilon() * dt) { res.status = 2; break; }
   }
@@ -797,9 +808,12 @@ int orc_cell_arnoldi(const orc_mech* m, const double* u, double p, int M, int mo
 }
 
 // Integrates n cells over [0, dt] in place.  acc/rej/status may be null.
-int orc_integrate(const orc_mech* m, const orc_opts* o, int64_t n, double* Y, double* T,
-                  const double* p, const double* S, double dt, double rtol, double atol,
-                  int32_t* acc, int32_t* rej, int32_t* status, int nthreads) {
+// As orc_integrate with per-cell first trial steps: h_io[c] > 0 (finite) is cell c's
+// h_0; on return h_io[c] holds the step to start the next call from (Result::h_next),
+// for cells with valid input.  h_io may be null.
+int orc_integrate_h(const orc_mech* m, const orc_opts* o, int64_t n, double* Y, double* T,
+                    const double* p, const double* S, double dt, double rtol, double atol,
+                    double* h_io, int32_t* acc, int32_t* rej, int32_t* status, int nthreads) {
   const int ns = m->n_species;
   if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
@@ -816,15 +830,22 @@ int orc_integrate(const orc_mech* m, const orc_opts* o, int64_t n, double* Y, do
         for (int k = 0; k <= ns; ++k) s[k] = S[k * n + c];
       }
       CellProblem prob{m, p[c], S ? s.data() : nullptr};
-      r = rok4e_one(prob, u, dt, rtol, atol, *o);
+      r = rok4e_one(prob, u, dt, rtol, atol, *o, nullptr, h_io ? h_io[c] : 0.0);
       for (int k = 0; k < ns; ++k) Y[k * n + c] = u[k];
       T[c] = u[ns];
+      if (h_io) h_io[c] = r.h_next;
     }
     if (acc) acc[c] = r.accepted;
     if (rej) rej[c] = r.rejected;
     if (status) status[c] = r.status;
   }
   return 0;
+}
+
+int orc_integrate(const orc_mech* m, const orc_opts* o, int64_t n, double* Y, double* T,
+                  const double* p, const double* S, double dt, double rtol, double atol,
+                  int32_t* acc, int32_t* rej, int32_t* status, int nthreads) {
+  return orc_integrate_h(m, o, n, Y, T, p, S, dt, rtol, atol, nullptr, acc, rej, status, nthreads);
 }
 
 // ROK4E on the linear problem u' = A u + c (A row-major n x n), u in place.
