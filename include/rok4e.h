@@ -147,6 +147,19 @@ int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* mech, double* Y, double*
                            const double* p, const double* S, double dt, double rtol,
                            double atol, void* stream);
 
+/* As rok4e_integrate_forced with per-cell first trial steps (the h_0 input of Algorithm
+ * a:ROK4E), for a caller that integrates the same cells over consecutive substeps:
+ * h_io[n_cells] (device, FP64, may be NULL) holds on input each cell's first trial step
+ * (<= 0 or non-finite: the option h0, else dt) and on output the step to start the next
+ * call from: the controller's proposal after the cell's last attempt, or, when the last
+ * accepted step had been shortened to end at dt, the larger of that proposal and the one
+ * made before the shortening.  Cells with invalid input keep their entry.  ROK4E only
+ * (ROK4E_ENOTSUP with a non-NULL h_io and ROK4E_METHOD_RKDP45).  S as for
+ * rok4e_integrate_forced. */
+int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* mech, double* Y, double* T, const double* p,
+                       const double* S, double* h_io, double dt, double rtol, double atol,
+                       void* stream);
+
 /* Launch tuning: integrates a copy of the given batch (Y, T, p as for rok4e_integrate;
  * the caller's arrays are not modified) once per waves-per-block choice 1..4 with the
  * handle's other options, times each with HIP events after a warm-up run, and keeps the

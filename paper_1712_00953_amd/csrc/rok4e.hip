@@ -50,8 +50,9 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m,
     CellState c{};
     c.status = 3;
     if (load_cell<L, ROWS>(m, P, cell, lane, u, s, p)) {
-      c = integrate_cell<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane);
+      c = integrate_cell<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane, P.hio ? P.hio[cell] : 0.0);
       store_cell<L, ROWS>(m, P, cell, lane, u);
+      if (P.hio) P.hio[cell] = c.hnext;
     }
     // every lane of the segment stores the same (segment-uniform) values
     P.acc[cell] = c.accepted;
@@ -125,7 +126,7 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_attempt(DevMech m, L
     if (W.first) {
       c.status = 3;
       if (valid) {
-        cell_start(P, c);
+        cell_start(P, c, P.hio ? P.hio[cell] : 0.0);
         run = cell_running(P, c);
       }
     } else {
@@ -162,6 +163,7 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_attempt(DevMech m, L
       P.acc[cell] = c.accepted;
       P.rej[cell] = c.rejected;
       P.status[cell] = c.status;
+      if (P.hio && valid) P.hio[cell] = c.hnext;
     }
     lds_sync();
   }
@@ -710,10 +712,11 @@ int rok4e_reserve(rok4e_mech* m, int64_t max_cells) {
   return ROK4E_OK;
 }
 
-int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* m, double* Y, double* T, const double* p,
-                           const double* S, double dt, double rtol, double atol, void* stream) {
+int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, const double* p,
+                       const double* S, double* h_io, double dt, double rtol, double atol, void* stream) {
   int rc = check_state_args(n_cells, m, Y, T, p);
   if (rc) return rc;
+  if (h_io && m->opt.method == ROK4E_METHOD_RKDP45) return ROK4E_ENOTSUP;
   if (!(dt > 0.0) || !std::isfinite(dt) || !(rtol > 0.0) || !(atol >= 0.0) || !std::isfinite(rtol) ||
       !std::isfinite(atol))
     return ROK4E_EINVAL;
@@ -726,6 +729,7 @@ int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
   P.dt = dt;
   P.rtol = rtol;
   P.atol = atol;
+  P.hio = h_io;
   LaunchShape sh;
   if (m->opt.method == ROK4E_METHOD_RKDP45) {
     if (m->opt.scheduling != ROK4E_PERSISTENT) return ROK4E_ENOTSUP;
@@ -759,9 +763,14 @@ int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
   return ROK4E_OK;
 }
 
+int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* m, double* Y, double* T, const double* p,
+                           const double* S, double dt, double rtol, double atol, void* stream) {
+  return rok4e_integrate_ex(n_cells, m, Y, T, p, S, nullptr, dt, rtol, atol, stream);
+}
+
 int rok4e_integrate(int64_t n_cells, rok4e_mech* m, double* Y, double* T, const double* p, double dt,
                     double rtol, double atol, void* stream) {
-  return rok4e_integrate_forced(n_cells, m, Y, T, p, nullptr, dt, rtol, atol, stream);
+  return rok4e_integrate_ex(n_cells, m, Y, T, p, nullptr, nullptr, dt, rtol, atol, stream);
 }
 
 int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T, const double* p,

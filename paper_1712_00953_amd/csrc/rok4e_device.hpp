@@ -82,6 +82,7 @@ struct Launch {
   int M, max_attempts, fixed_steps;
   unsigned int* queue;
   int32_t* acc; int32_t* rej; int32_t* status;
+  double* hio;   // [n] per-cell first trial step in, step for the next call out (or null)
   int seg_bytes, off_k, off_H, off_LU, off_rdiag;
 };
 

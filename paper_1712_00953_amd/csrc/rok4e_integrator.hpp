@@ -268,12 +268,18 @@ __device__ __forceinline__ void stage_solve(const double (&F)[ROWS], const doubl
 // or done, 1 attempt limit, 2 step size underflow, 3 invalid input.
 struct CellState {
   double t, h, lerr_prev;   // time, step, ln of the last accepted error (0: err_prev = 1)
+  double hnext;             // step for a following call: the last proposal, or the larger
+                            // of it and the proposal made before the last accepted step
+                            // was shortened to end at dt
   int attempts, accepted, rejected, steps_done, status, Meff, basis_valid, pad;
 };
 
-__device__ __forceinline__ void cell_start(const Launch& P, CellState& c) {
+// h0c > 0 (finite): the cell's own first trial step (the h_0 input of the algorithm).
+__device__ __forceinline__ void cell_start(const Launch& P, CellState& c, double h0c = 0.0) {
   c.t = 0.0;
-  c.h = P.fixed_steps > 0 ? P.dt / P.fixed_steps : (P.h0 > 0.0 ? P.h0 : P.dt);
+  c.h = P.fixed_steps > 0 ? P.dt / P.fixed_steps
+                          : (h0c > 0.0 && __builtin_isfinite(h0c) ? h0c : (P.h0 > 0.0 ? P.h0 : P.dt));
+  c.hnext = c.h;
   c.lerr_prev = 0.0;
   c.attempts = c.accepted = c.rejected = c.steps_done = c.status = c.Meff = c.basis_valid = c.pad = 0;
 }
@@ -311,6 +317,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
     h = dt - c.t;
     last = true;
   }
+  const double hprop = c.h;
   if (!c.basis_valid) {
     RT wbase[ROWS];
     RhsBase base;
@@ -323,6 +330,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
     ++c.attempts;
     ++c.rejected;
     c.h = h * 0.2;
+    c.hnext = c.h;
     if (c.h < tiny) c.status = 2;
     return;
   }
@@ -404,8 +412,10 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
     c.lerr_prev = lerr;
     ++c.accepted;
     c.basis_valid = 0;
+    c.hnext = last ? fmax(hstar, hprop) : hstar;
   } else {
     ++c.rejected;
+    c.hnext = hstar;
   }
   c.h = hstar;
   if (c.t < dt && c.h < tiny) c.status = 2;
@@ -416,9 +426,9 @@ template <int L, int ROWS, int MMAX, class RT>
 __device__ __forceinline__ CellState integrate_cell(const DevMech& m, const MechLds& tab,
                                                     const Launch& P, double (&u)[ROWS], double p,
                                                     const double (&s)[ROWS], const SegLds<RT>& S,
-                                                    int lane) {
+                                                    int lane, double h0c = 0.0) {
   CellState c;
-  cell_start(P, c);
+  cell_start(P, c, h0c);
   double fn[ROWS], Q[ROWS][MMAX];
   while (cell_running(P, c)) cell_attempt<L, ROWS, MMAX, RT>(m, tab, P, u, p, s, S, lane, c, fn, Q);
   return c;

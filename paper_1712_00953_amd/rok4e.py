@@ -26,6 +26,7 @@ CELL_OK, CELL_MAX_ATTEMPTS, CELL_STEP_UNDERFLOW, CELL_BAD_INPUT = 0, 1, 2, 3
 
 EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "rok4e_set_options",
            "rok4e_get_options", "rok4e_reserve", "rok4e_integrate", "rok4e_integrate_forced",
+           "rok4e_integrate_ex",
            "rok4e_tune", "rok4e_rhs", "rok4e_arnoldi", "rok4e_transport", "rok4e_split_workspace_bytes",
            "rok4e_split_step", "rok4e_get_stats", "rok4e_cell_stats_ptr",
            "rok4e_copy_cell_stats", "rok4e_strerror"]
@@ -86,6 +87,7 @@ def load():
         lib.rok4e_reserve.argtypes = [vp, i64]
         lib.rok4e_integrate.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_forced.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
+        lib.rok4e_integrate_ex.argtypes = [i64, vp, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_tune.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_float), vp]
         lib.rok4e_rhs.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
@@ -134,6 +136,19 @@ def _ptr(t):
     if hasattr(t, "data_ptr"):
         return C.c_void_p(t.data_ptr())
     return C.c_void_p(int(t))
+
+
+def _need(t, count, name):
+    """Host-side check of a device operand before its pointer goes to a kernel: float64,
+    contiguous, on a GPU, at least count elements (the kernels index it up to there)."""
+    if t is None:
+        return
+    if not hasattr(t, "data_ptr"):
+        raise TypeError(f"{name}: expected a device tensor")
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() < count:
+        raise ValueError(f"{name}: need a contiguous float64 device tensor with >= {count} elements, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
 
 
 def _stream(stream):
@@ -190,11 +205,16 @@ class Mech:
     def reserve(self, n_cells: int):
         _check(load().rok4e_reserve(self._h, int(n_cells)), "rok4e_reserve")
 
-    def integrate(self, Y, T, p, dt, rtol, atol, S=None, stream=None, n_cells=None):
-        """In-place integration of Y [ns, n], T [n] (float64 device tensors) over dt."""
+    def integrate(self, Y, T, p, dt, rtol, atol, S=None, stream=None, n_cells=None, h=None):
+        """In-place integration of Y [ns, n], T [n] (float64 device tensors) over dt.
+        h (float64 device tensor [n], optional): per-cell first trial steps in, the steps
+        to start the next call from out (rok4e_integrate_ex)."""
         n = int(T.shape[0]) if n_cells is None else int(n_cells)
-        rc = load().rok4e_integrate_forced(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(S), float(dt),
-                                           float(rtol), float(atol), _stream(stream))
+        ns = self.n_species
+        for t, cnt, name in ((Y, ns * n, "Y"), (T, n, "T"), (p, n, "p"), (S, (ns + 1) * n, "S"), (h, n, "h")):
+            _need(t, cnt, name)
+        rc = load().rok4e_integrate_ex(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(S), _ptr(h), float(dt),
+                                       float(rtol), float(atol), _stream(stream))
         _check(rc, "rok4e_integrate")
         self.n_last = n
 

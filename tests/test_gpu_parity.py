@@ -164,6 +164,53 @@ def test_projected_solve_with_row_interchanges(R, orc, fixed, dt):
     m.close()
 
 
+@pytest.mark.parametrize("sched", ["persistent", "per_attempt"])
+def test_carried_first_step_parity(R, orc, sched):
+    """Two consecutive substeps, the second started from the per-cell steps the first
+    handed on (rok4e_integrate_ex): states, counts and the handed-on steps against the
+    oracle's chained calls, with its FMA twin's chain as the rounding envelope."""
+    import torch
+    w = synth.workload(1, a_scale=A_SCALE, n_cells=256)
+    st = w.states
+    n = st.n_cells
+
+    def chain(fma):
+        h = np.zeros(n)
+        Y, T, a1, r1, s1 = orc.integrate(w.mech, st.Y, st.T, st.p, w.dt, w.rtol, w.atol, w.M, h_io=h, fma=fma)
+        h1 = h.copy()
+        Y, T, a2, r2, s2 = orc.integrate(w.mech, Y, T, st.p, w.dt, w.rtol, w.atol, w.M, h_io=h, fma=fma)
+        return (Y, T, a2, r2, s2), h1, h, a1 + r1
+
+    o, oh1, oh2, oatt1 = chain(False)
+    f, fh1, fh2, _ = chain(True)
+    env_rel = max(relative(f, o), float(np.max(np.abs(fh2 - oh2) / oh2)))
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT,
+               scheduling=R.PER_ATTEMPT if sched == "per_attempt" else R.PERSISTENT)
+    Y, T, p = dev_state(st)
+    h = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    m.integrate(Y, T, p, w.dt, w.rtol, w.atol, h=h)
+    torch.cuda.synchronize()
+    gh1 = h.cpu().numpy()
+    m.integrate(Y, T, p, w.dt, w.rtol, w.atol, h=h)
+    acc = torch.zeros(n, dtype=torch.int32)
+    rej = torch.zeros(n, dtype=torch.int32)
+    sta = torch.zeros(n, dtype=torch.int32)
+    m.cell_stats(acc, rej, sta)
+    torch.cuda.synchronize()
+    g = (Y.cpu().numpy(), T.cpu().numpy(), acc.numpy(), rej.numpy(), sta.numpy())
+    gh2 = h.cpu().numpy()
+    d = dict(rel=relative(g, o), env_rel=env_rel, **parity(g, o),
+             h1_rel=float(np.max(np.abs(gh1 - oh1) / oh1)), h2_rel=float(np.max(np.abs(gh2 - oh2) / oh2)),
+             h1_over_dt_median=float(np.median(oh1) / w.dt))
+    _report(f"carried step {sched}", d)
+    assert np.all(g[4] == 0) and np.all(o[4] == 0)
+    assert np.all(oh1 < w.dt)            # the carried start differs from the default
+    assert d["match_frac"] == 1.0
+    bar = max(1e-10, 4 * env_rel)
+    assert d["rel"] <= bar and d["h1_rel"] <= bar and d["h2_rel"] <= bar
+    m.close()
+
+
 @pytest.mark.parametrize("cfg,n", [(1, 1024), (2, 512), (3, 512)])
 def test_adaptive_parity_fp64(R, orc, cfg, n):
     w = synth.workload(cfg, a_scale=A_SCALE)
