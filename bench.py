@@ -245,6 +245,66 @@ def run_splitting(R, torch, synth, nx=64, h=1e-6, reps=3):
     return out
 
 
+def run_study(R, torch, synth, n_cells=16384, t_end=1e-5, rtol=1e-4, atol=1e-8):
+    """Efficiency study in the manner of Sec. 5 (Fig. 5): the cells integrate the same
+    physical window t_end as a sequence of calls of length h_CFL (each call restarts the
+    integrator at h0 = h_CFL, as a CFD code calling the reaction substep would), for
+    h_CFL = 1e-9 .. 1e-5 s, with ROK4E at M = 4, 6, 8 and the explicit Dormand-Prince
+    5(4) pair, at rtol = 1e-4, atol = 1e-8.  Cells: a stratified draw from the 53-species
+    flame slice, on the calibrated mechanism (pre-exponential factors x 1e-8) and on a
+    stiffer one (x 1e-5).  Reported per point: GPU time of the whole window (HIP events
+    around the call sequence), attempts, and the error of the final state against ROK4E
+    M = 8 at rtol = 1e-10, atol = 1e-14 over the window in one call (max relative error
+    of T, 99th percentile over cells of the largest species error relative to
+    max(|Y|, atol / rtol), the size below which the absolute tolerance governs)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for a_scale in (A_SCALE, 1e-5):
+        w = synth.workload(2, a_scale=a_scale)
+        idx = synth.stratified_sample(w.states.T, n_cells, 991)
+        st = w.states.subset(idx)
+        Y0 = torch.tensor(st.Y, dtype=torch.float64, device=dev)
+        T0 = torch.tensor(st.T, dtype=torch.float64, device=dev)
+        p = torch.tensor(st.p, dtype=torch.float64, device=dev)
+        ref = R.Mech(w.mech, M=8, max_attempts=10_000_000)
+        Yr, Tr = Y0.clone(), T0.clone()
+        ref.integrate(Yr, Tr, p, t_end, 1e-10, 1e-14)
+        torch.cuda.synchronize()
+        Yr, Tr = Yr.cpu().numpy(), Tr.cpu().numpy()
+        ok_ref = ref.stats()["status_count"][0] == st.n_cells
+        ref.close()
+        for method, M in (("rok4e", 4), ("rok4e", 6), ("rok4e", 8), ("rkdp45", 0)):
+            m = R.Mech(w.mech, M=max(M, 1), max_attempts=10_000_000,
+                       method=R.METHOD_RKDP45 if method == "rkdp45" else R.METHOD_ROK4E)
+            for h_cfl in (1e-9, 1e-8, 1e-7, 1e-6, 1e-5):
+                calls = int(round(t_end / h_cfl))
+                Y, T = Y0.clone(), T0.clone()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                for _ in range(calls):
+                    m.integrate(Y, T, p, h_cfl, rtol, atol)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                s = m.stats()
+                att = s["accepted"] + s["rejected"]        # last call only
+                bad = st.n_cells - s["status_count"][0]   # last call only
+                Yg, Tg = Y.cpu().numpy(), T.cpu().numpy()
+                errT = float(np.max(np.abs(Tg - Tr) / Tr))
+                errY = float(np.percentile(np.max(np.abs(Yg - Yr) / np.maximum(np.abs(Yr), atol / rtol), axis=0),
+                                           99))
+                rows.append(dict(a_scale=a_scale, method=method, M=M or None, h_cfl=h_cfl, calls=calls,
+                                 gpu_ms=ms, attempts_last_call=int(att), failed_cells_last_call=int(bad),
+                                 err_T_max=errT, err_Y_p99=errY, reference_ok=bool(ok_ref)))
+                log(f"study a={a_scale:g} {method}{'' if not M else f' M={M}'} h_cfl={h_cfl:g}: "
+                    f"{ms:9.2f} ms, errT {errT:.2e}, errY {errY:.2e}")
+            m.close()
+    return dict(n_cells=n_cells, t_end=t_end, rtol=rtol, atol=atol, rows=rows)
+
+
 def run_cpu_baseline(w, target_s=10.0):
     """The oracle on a uniformly drawn sample of the batch, all host threads."""
     from oracle import oracle as O
@@ -281,6 +341,9 @@ def main():
                          "kernel of known size, to scale HBM byte counters)")
     ap.add_argument("--print-source-hash", action="store_true",
                     help="print the kernel source hash that a traffic measurement must carry")
+    ap.add_argument("--study", action="store_true",
+                    help="run only the efficiency study (ROK4E M = 4, 6, 8 vs Dormand-Prince 5(4) "
+                         "over h_CFL = 1e-9 .. 1e-5) and print it as one JSON line")
     args = ap.parse_args()
     if args.print_source_hash:
         print(kernel_source_hash())
@@ -297,6 +360,9 @@ def main():
     R.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.study:
+        print(json.dumps({"study": "efficiency vs h_CFL", **run_study(R, torch, synth)}), flush=True)
+        return
     w = synth.workload(2, a_scale=A_SCALE)
     log(f"workload {w.name}: {w.states.n_cells} cells, M={w.M}, dt={w.dt}")
     fp64 = run_gpu(w, R.FP64, args.steps, args.warmup, R, torch)
