@@ -10,7 +10,7 @@ Prints one JSON line: FP64 cell-integrations/s as `value`, the mixed-precision f
 and speed-up beside it, the roofline of the integration kernel (algorithmic FP64
 operations / kernel time against the FP64 vector peak), the standalone right-hand-side
 and Arnoldi kernels against the same peak, persistent vs per-attempt scheduling on the
-262,144-cell bimodal batch, one Simpler balanced splitting step on a 64^3 grid, and the
+262,144-cell bimodal batch, one Simpler balanced splitting step on a 128^3 grid at CFL 0.5, and the
 CPU oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
@@ -191,10 +191,11 @@ def run_schedules(R, torch, synth):
     return out
 
 
-def run_splitting(R, torch, synth, nx=64, h=1e-6, reps=3):
+def run_splitting(R, torch, synth, nx=128, h=5e-6, reps=2):
     """One Simpler balanced splitting step on an nx^3 periodic grid carrying the 53-species
-    flame profile along x (advection 10 m/s, diffusivity 2e-5 m^2/s, dx = 1e-4 m): the
-    whole step, and its reaction substep alone (same forcing), timed with HIP events."""
+    flame profile along x (advection 10 m/s, diffusivity 2e-5 m^2/s, dx = 1e-4 m, so
+    h = 5e-6 s is CFL 0.5): the whole step, and its reaction substep alone (same
+    forcing), timed with HIP events."""
     w = synth.workload(2, a_scale=A_SCALE, n_cells=4)
     mech = w.mech
     ns = mech.n_species

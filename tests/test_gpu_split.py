@@ -113,6 +113,45 @@ def test_simpler_preserves_steady_state_strang_drifts(R):
     m.close()
 
 
+def test_steady_state_on_the_full_grid(R):
+    """The 128^3 grid (2,097,152 cells) at CFL 0.5 (h = 0.5 dx / vel = 5e-6 s) with the
+    53-species flame profile along x made a discrete steady state of T + R + src by its
+    forcing: 100 Simpler steps keep it to 1e-8 relative; two Strang steps leave it."""
+    import torch
+    nx = 128
+    n = nx ** 3
+    w = synth.workload(2, a_scale=A_SCALE, n_cells=4)
+    st = synth.states_flame(w.mech, nx, nx * nx, 4600)
+    ns = w.mech.n_species
+    h = 0.5 * DX / VEL
+    g = R.grid(nx, nx, nx, DX, VEL, DIFF)
+    m = R.Mech(w.mech, M=w.M)
+    Y0, T0, p = _dev(st.Y, st.T, st.p)
+    del st
+    dY, dT = torch.empty_like(Y0), torch.empty_like(T0)
+    m.rhs(Y0, T0, p, dY, dT)
+    src = torch.empty((ns + 1) * n, dtype=torch.float64, device="cuda:0")
+    R.transport(g, ns, Y0, T0, src)
+    src.add_(torch.cat([dY.reshape(-1), dT])).neg_()
+    del dY, dT
+    work = torch.empty(m.workspace_bytes(g) // 8, dtype=torch.float64, device="cuda:0")
+    dev = {}
+    for name, scheme, steps in (("simpler", R.SPLIT_SIMPLER, 100), ("strang", R.SPLIT_STRANG, 2)):
+        Y, T = Y0.clone(), T0.clone()
+        for _ in range(steps):
+            m.split_step(g, scheme, Y, T, p, h, 1e-8, 1e-14, work, src=src)
+        torch.cuda.synchronize()
+        assert m.stats()["status_count"][0] == n
+        rel = torch.maximum((Y - Y0).abs().amax() / Y0.abs().amax().clamp_min(1e-300),
+                            ((T - T0).abs() / T0).amax())
+        dev[name] = float(rel)
+        print(f"\n[steady 128^3] {name}: {steps} steps, max deviation {dev[name]:.3e}", flush=True)
+        del Y, T
+    assert dev["simpler"] <= 1e-8
+    assert dev["strang"] >= 1e-6
+    m.close()
+
+
 def test_split_step_argument_errors(R):
     import torch
     w = synth.workload(1, a_scale=A_SCALE, n_cells=4)
