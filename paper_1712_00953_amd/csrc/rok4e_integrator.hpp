@@ -160,28 +160,24 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
 // (the same operations on the same values as interchanging all rows first and
 // substituting with the permuted unit-lower factor).  Every lane of the segment
 // computes the same values in registers, two rows at a time: r is the pivot row k, s
-// row k + 1, nx row k + 2 loaded one step ahead.  U goes to LU (upper part), the
-// reciprocals of its diagonal to rdiag.  False when a pivot is zero.
+// row k + 1 (one step per scheduling region, which keeps the register demand at two
+// rows).  U goes to LU (upper part), the reciprocals of its diagonal to rdiag.  False
+// when a pivot is zero.
 template <int MMAX>
 __device__ __forceinline__ bool lu_factor(const double* __restrict__ H, double hg, double* __restrict__ LU,
                                           double* __restrict__ rdiag, unsigned& piv) {
-  double r[MMAX], nx[MMAX];
+  double r[MMAX];
 #pragma unroll
   for (int j = 0; j < MMAX; ++j) r[j] = (j == 0 ? 1.0 : 0.0) - hg * H[j];
-#pragma unroll
-  for (int j = 0; j < MMAX; ++j) nx[j] = (j == 1 ? 1.0 : 0.0) - hg * H[MMAX + j];
   piv = 0u;
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < MMAX; ++k) {
+    __builtin_amdgcn_sched_barrier(0);
     double s[MMAX];
     if (k + 1 < MMAX) {
 #pragma unroll
-      for (int j = k; j < MMAX; ++j) s[j] = nx[j];
-      if (k + 2 < MMAX) {
-#pragma unroll
-        for (int j = k + 1; j < MMAX; ++j) nx[j] = (j == k + 2 ? 1.0 : 0.0) - hg * H[(k + 2) * MMAX + j];
-      }
+      for (int j = k; j < MMAX; ++j) s[j] = (j == k + 1 ? 1.0 : 0.0) - hg * H[(k + 1) * MMAX + j];
       const bool pv = fabs(s[k]) > fabs(r[k]);
       piv |= pv ? (1u << k) : 0u;
 #pragma unroll
@@ -207,10 +203,13 @@ __device__ __forceinline__ bool lu_factor(const double* __restrict__ H, double h
   return ok;
 }
 
-// x <- A^{-1} x for a segment-uniform vector x with the factors of lu_factor.
+// x <- A^{-1} x for a segment-uniform vector x with the factors of lu_factor.  The rows
+// of U are loaded one back-substitution step at a time (a scheduling barrier per row):
+// hoisting all of them at once costs more registers than the kernel has at three waves
+// per SIMD, and the spills cost more than the exposed load latency.
 template <int MMAX>
-__device__ __forceinline__ void lu_solve(const double* __restrict__ LU, const double* __restrict__ rdiag,
-                                         unsigned piv, double (&x)[MMAX]) {
+__device__ __forceinline__ void lu_solve(const double* LU, const double* rdiag, unsigned piv,
+                                         double (&x)[MMAX]) {
 #pragma unroll
   for (int k = 0; k + 1 < MMAX; ++k) {
     const bool pv = ((piv >> k) & 1u) != 0u;
@@ -220,6 +219,7 @@ __device__ __forceinline__ void lu_solve(const double* __restrict__ LU, const do
   }
 #pragma unroll
   for (int i = MMAX - 1; i >= 0; --i) {
+    __builtin_amdgcn_sched_barrier(0);
     double sacc = x[i];
 #pragma unroll
     for (int j = i + 1; j < MMAX; ++j) sacc = sacc - LU[i * MMAX + j] * x[j];
