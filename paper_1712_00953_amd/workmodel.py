@@ -7,10 +7,11 @@ cross HBM: Y, T and p read, Y and T written.
 
 Per attempt (Algorithm a:ROK4E, Sec. 4.3):
 * a new basis (after an accepted step, and at the start) costs f(u_n), M finite-
-  difference Jacobian-vector products (one f each, Sec. 4.3: "M evaluations of f"),
-  the modified Gram-Schmidt Arnoldi process, the M x M factorisation, the four stages
-  with two further evaluations of f (stage 4 reuses the stage-3 argument), the
-  solution, the embedded error and the controller;
+  difference Jacobian-vector products (one f each, the cost Sec. 4.3 assigns to the
+  basis), the Arnoldi process (modified Gram-Schmidt and one re-orthogonalisation
+  pass), the M x M factorisation, the four stages with two further evaluations of f
+  (stage 4 reuses the stage-3 argument), the solution, the embedded error and the
+  controller;
 * a retry after a rejection reuses the basis of the same u_n: two evaluations of f, the
   factorisation, the stages, the error and the controller.
 """
@@ -42,7 +43,9 @@ def attempt_ops(mech, M: int) -> dict:
     jvp = cf + 4 * N                        # perturbation and difference quotient
     arnoldi = 3 * N + 2 * N + 4             # |f_n|, first vector, |u| and delta
     for j in range(Me):
-        arnoldi += 2 * N + 4 * N * (j + 1) + 3 * N + 2   # |w|, MGS, |w| and normalise
+        # |w|, modified Gram-Schmidt, the re-orthogonalisation pass (projections, removal,
+        # coefficients added to H), |w| and normalise
+        arnoldi += 2 * N + 4 * N * (j + 1) + 4 * N * (j + 1) + (j + 1) + 3 * N + 2
     lu = 3 * Me * Me + Me * Me + Me          # build I - h g H, Hessenberg LU
     solve = Me * Me + 2 * Me
     stage = 4 * N * Me + solve + Me + 2 * N  # Q^T F, solve, z - y, Q w, k
