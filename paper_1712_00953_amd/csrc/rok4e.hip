@@ -403,7 +403,10 @@ int ensure_image(rok4e_mech* m) {
   const int off_spec = al16(3 * nrp * 16);
   const int off_rxo = al16(off_spec + 4 * lp * 8);
   const int off_spos = al16(off_rxo + nrp * 8);
-  const int bytes = al16(off_spos + lp * 4);
+  // mixed precision: (b_f, E_f, b_r, E_r) once more in FP32 for the Jacobian-vector
+  // products
+  const int off_bE32 = rb == 4 ? al16(off_spos + lp * 4) : 0;
+  const int bytes = rb == 4 ? al16(off_bE32 + nrp * 16) : al16(off_spos + lp * 4);
   std::vector<char> img(bytes, 0);
   // (ln A_f, ln A_r), (b_f, E_f), (b_r, E_r); m->par holds ln A_f, b_f, E_f, ln A_r,
   // b_r, E_r, each [nr]
@@ -432,12 +435,22 @@ int ensure_image(rok4e_mech* m) {
   }
   int* spos = (int*)(img.data() + off_spos);
   for (int r = 0; r < lp; ++r) spos[r] = r < ns ? pl.pos[r] : ns;
+  if (off_bE32) {
+    float* be = (float*)(img.data() + off_bE32);
+    for (int q = 0; q < nr; ++q) {
+      const int j = pl.order[q];
+      be[4 * q] = (float)m->par[1 * nr + j];
+      be[4 * q + 1] = (float)m->par[2 * nr + j];
+      be[4 * q + 2] = (float)m->par[4 * nr + j];
+      be[4 * q + 3] = (float)m->par[5 * nr + j];
+    }
+  }
   if (m->d_image) (void)hipFree(m->d_image);
   m->d_image = nullptr;
   hipError_t e = hipMalloc(&m->d_image, bytes);
   if (e == hipSuccess) e = hipMemcpy(m->d_image, img.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e);
-  m->dm = DevMech{ns, nr, nrp, lp, off_spec, off_rxo, off_spos, bytes, (const int4*)m->d_image};
+  m->dm = DevMech{ns, nr, nrp, lp, off_spec, off_rxo, off_spos, off_bE32, bytes, (const int4*)m->d_image};
   m->image_key = key;
   return ROK4E_OK;
 }

@@ -57,7 +57,7 @@ constexpr double E1 = BH1 - B1, E2 = BH2 - B2, E3 = BH3 - 0.0, E4 = 0.0 - B4;
 // order of the production sums).
 struct DevMech {
   int ns, nr, nrp, lp;
-  int off_spec, off_rxo, off_spos, image_bytes;
+  int off_spec, off_rxo, off_spos, off_bE32, image_bytes;   // off_bE32: 0 when absent
   const int4* image;
 };
 
@@ -67,6 +67,7 @@ struct MechLds {
   const double* W; const double* invW; const double* cp; const double* hf;
   const uint2* rxo;
   const int* spos;
+  const float4* bE32;   // (b_f, E_f, b_r, E_r) in FP32, mixed-precision images only
 };
 
 // A pair of rate-type values (the forward and reverse rate constants of a reaction).
@@ -100,6 +101,7 @@ __device__ __forceinline__ MechLds load_mech_lds(const DevMech& m, char* lds) {
   t.W = sp; t.invW = sp + m.lp; t.cp = sp + 2 * m.lp; t.hf = sp + 3 * m.lp;
   t.rxo = (const uint2*)(lds + m.off_rxo);
   t.spos = (const int*)(lds + m.off_spos);
+  t.bE32 = m.off_bE32 ? (const float4*)(lds + m.off_bE32) : nullptr;
   return t;
 }
 
@@ -507,11 +509,22 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
   lds_sync();
 #pragma unroll ROK4E_RX_UNROLL
   for (int j = lane; j < m.nr; j += L) {
-    const double2 bEf = t.bEf[j], bEr = t.bEr[j];
+    // the exponents' increments b dlnT - E d(1/RT); the mixed form reads b and E from
+    // the FP32 table (half the bytes; its increments are FP32 anyway)
+    double dlf, dlr;
+    if constexpr (sizeof(RT) == 4) {
+      const float4 be = t.bE32[j];
+      dlf = (double)be.x * dlnT - (double)be.y * dinvRT;
+      dlr = (double)be.z * dlnT - (double)be.w * dinvRT;
+    } else {
+      const double2 bEf = t.bEf[j], bEr = t.bEr[j];
+      dlf = bEf.x * dlnT - bEf.y * dinvRT;
+      dlr = bEr.x * dlnT - bEr.y * dinvRT;
+    }
     const auto kj = S.k[j];
     const RT kf = kj.x, kr = kj.y;
-    const RT dkf = kf * (RT)expm1_small(bEf.x * dlnT - bEf.y * dinvRT);
-    const RT dkr = kr * (RT)expm1_small(bEr.x * dlnT - bEr.y * dinvRT);
+    const RT dkf = kf * (RT)expm1_small(dlf);
+    const RT dkr = kr * (RT)expm1_small(dlr);
     const uint2 o = t.rxo[j];
     const RT* a0 = (const RT*)(rb + (o.x & 0xFFFFu));
     const RT* a1 = (const RT*)(rb + (o.x >> 16));
