@@ -414,6 +414,22 @@ def test_edge_cases(R, orc):
     o = orc.integrate(w.mech, st.Y, st.T, st.p, w.dt, w.rtol, w.atol, w.M, max_attempts=1)
     np.testing.assert_array_equal(g[4], o[4])
     assert np.all(g[4] == 1)
+    # per-cell steps: refused by the binding when too short or of the wrong type, by the
+    # library for the explicit method; an invalid cell keeps its entry
+    h = torch.full((st.n_cells,), 0.5 * w.dt, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(ValueError):
+        m.integrate(Y, T, p, w.dt, w.rtol, w.atol, h=h[:2])
+    with pytest.raises(ValueError):
+        m.integrate(Y, T, p, w.dt, w.rtol, w.atol, h=h.float())
+    m.set_options(M=w.M, method=R.METHOD_RKDP45)
+    with pytest.raises(R.Rok4eError):
+        m.integrate(Y, T, p, w.dt, w.rtol, w.atol, h=h)
+    m.set_options(M=w.M)
+    Yb_d, Tb_d, p_d = dev_state(sb)
+    m.integrate(Yb_d, Tb_d, p_d, w.dt, w.rtol, w.atol, h=h)
+    torch.cuda.synchronize()
+    hh = h.cpu().numpy()
+    assert np.all(hh[1:4] == 0.5 * w.dt) and hh[0] != 0.5 * w.dt and hh[4] != 0.5 * w.dt
     m.close()
 
 
