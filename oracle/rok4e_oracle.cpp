@@ -34,7 +34,12 @@
 //   - Arnoldi: M_eff = min(M, N); stop early when the new vector's norm falls below
 //     1e-12 of the norm before orthogonalisation; ||f_n|| = 0 gives M_eff = 0;
 //   - after a rejected step the basis of the same u_n is reused (identical result);
-//   - non-finite u* or err counts as a rejection with err = +inf.
+//   - non-finite u* or err counts as a rejection with err = +inf;
+//   - h_0 = dt unless given (per cell in orc_integrate_h, which also returns the step to
+//     start the next call from: the controller's last proposal, or the larger of it and
+//     the proposal made before the last step was shortened to end at dt).
+// Also here, for the efficiency study of Sec. 5: the explicit Dormand-Prince 5(4) pair
+// (published tableau, first-same-as-last, the same error norm, elementary controller).
 //
 // Built with -O2 -fno-fast-math -ffp-contract=off so each operation rounds once.
 
