@@ -120,6 +120,7 @@ def run_gpu(w, precision, steps, warmup, R, torch):
     torch.cuda.synchronize()
     m.close()
     S = (acc + rej).numpy()
+    Yl, Tl = copies[-1][0].cpu().numpy(), copies[-1][1].cpu().numpy()
     if stats["status_count"][0] != n:
         raise RuntimeError(f"cells failed: {stats}")
     ops = workmodel.batch_ops(w.mech, w.M, stats["accepted"], stats["rejected"])
@@ -133,7 +134,8 @@ def run_gpu(w, precision, steps, warmup, R, torch):
                 bytes=workmodel.state_bytes(w.mech, n),
                 attempts_per_cell={q: int(np.percentile(S, float(q[1:]))) for q in ("p50", "p90", "p99")}
                 | {"min": int(S.min()), "max": int(S.max()), "mean": float(S.mean())},
-                attempts_per_s=(stats["accepted"] + stats["rejected"]) / kavg)
+                attempts_per_s=(stats["accepted"] + stats["rejected"]) / kavg,
+                final_state=(Yl, Tl))
 
 
 def run_subsystems(w, R, torch, reps=5):
@@ -451,11 +453,19 @@ def main():
             "fetch_bytes_per_launch", "write_bytes_per_launch", "copy_scale_fetch", "copy_scale_write",
             "profile")}
     if mixed is not None:
+        # error of the mixed result against the FP64 result of the same batch (every cell;
+        # species above 1e-14 and T)
+        (Ym, Tm), (Yd, Td) = mixed["final_state"], fp64["final_state"]
+        graded = np.maximum(np.abs(Ym), np.abs(Yd)) >= 1e-14
+        relY = np.abs(Ym - Yd)[graded] / np.abs(Yd)[graded]
+        relT = np.abs(Tm - Td) / np.abs(Td)
         out["mixed"] = {"value": mixed["cells_per_s"], "unit": "cell-integrations/s",
                         "ms_per_step": mixed["ms_per_step"], "dtype": "f32 rates / f64 state",
                         "speedup_vs_fp64": mixed["cells_per_s"] / fp64["cells_per_s"],
                         "attempts_per_step": mixed["attempts"],
-                        "tflops_fp64_equivalent": mixed["tflops"]}
+                        "tflops_fp64_equivalent": mixed["tflops"],
+                        "max_rel_err_vs_fp64": float(max(relY.max(), relT.max())),
+                        "p99_rel_err_vs_fp64": float(np.percentile(relY, 99))}
     if subsystems is not None:
         out["subsystems"] = subsystems
     if schedules is not None:

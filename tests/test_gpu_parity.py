@@ -248,22 +248,32 @@ def test_adaptive_parity_fp64_cfg4(R, orc):
 
 
 @pytest.mark.parametrize("cfg,n,rtol,tol", [(1, 512, 1e-6, 1e-5), (2, 512, 1e-6, 1e-5),
-                                            (4, 128, 1e-6, 1e-4)])
+                                            (4, 128, 1e-6, 1e-4), (2, 256, 1e-8, 1e-4),
+                                            (4, 128, 1e-8, 1e-3)])
 def test_mixed_parity(R, orc, cfg, n, rtol, tol):
+    """Mixed FP32/FP64 against the FP64 oracle and against the FP64 GPU path on the same
+    cells.  The bar at rtol = 1e-6 is the stated one (1e-5 relative; 1e-4 on the
+    111-species workload, see the module notes); at rtol = 1e-8 the error is reported,
+    with a sanity bar only: the tighter tolerance does not remove the FP32 rounding of
+    the rates, so the mixed error stays near its rtol = 1e-6 level."""
     w = synth.workload(cfg, a_scale=A_SCALE)
     idx = synth.stratified_sample(w.states.T, n, 200 + cfg)
     st = w.states.subset(idx)
     m = R.Mech(w.mech, M=w.M, precision=R.MIXED, max_attempts=MAX_ATT)
     g = gpu_integrate(m, st, w.dt, rtol, w.atol)
+    m.close()
+    m64 = R.Mech(w.mech, M=w.M, precision=R.FP64, max_attempts=MAX_ATT)
+    g64 = gpu_integrate(m64, st, w.dt, rtol, w.atol)
+    m64.close()
     o, env = envelope(orc, w, st, w.dt, rtol, w.atol, max_attempts=MAX_ATT)
     mx, p99 = normalized(g, o, rtol, w.atol)
     d = dict(norm_max=mx, norm_p99=p99, **env, **parity_all(g, o))
     _report(f"mixed cfg{cfg} rtol={rtol:g}", d)
-    assert np.all(g[4] == 0)
-    d.update(rel=relative(g, o))
-    _report(f"mixed cfg{cfg} relative", dict(rel=d["rel"], bar=tol))
+    assert np.all(g[4] == 0) and np.all(g64[4] == 0)
+    d.update(rel=relative(g, o), rel_vs_gpu_fp64=relative(g, g64), fp64_rel=relative(g64, o))
+    _report(f"mixed cfg{cfg} rtol={rtol:g} relative",
+            dict(rel=d["rel"], rel_vs_gpu_fp64=d["rel_vs_gpu_fp64"], fp64_rel=d["fp64_rel"], bar=tol))
     assert d["rel"] <= tol
-    m.close()
 
 
 def test_layouts_agree_and_runs_are_deterministic(R, orc):
