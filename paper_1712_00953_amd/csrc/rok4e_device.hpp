@@ -468,11 +468,28 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
 // the compute type instead of the absolute accuracy eps |f| of a difference of two
 // evaluations.  The increments of the scalar state functions (rho, ln T, 1/(Ru T)) are
 // FP64.
-template <int L, int ROWS, class RT>
+// Base-state concentrations of the reactions one lane evaluates (NIT iterations of L
+// reactions, four species slots each), gathered once per basis so that each of the M
+// Jacobian-vector products reads only the increments from LDS.  At three waves per SIMD
+// the compiler keeps this array in the lane's private (scratch) memory, so the reads go
+// through the vector-memory path, which has spare bandwidth, instead of the LDS, which
+// bounds the products.
+template <int NIT, class RT>
+struct ConcCache {
+  RT c[NIT > 0 ? NIT : 1][4];
+};
+
+// Iterations cached for a layout (0: the products read the base concentrations from LDS):
+// six for the one-row, M <= 8 layout (up to 384 reactions at 64 lanes).
+template <int L, int ROWS, int MMAX>
+constexpr int jvp_cache_iters() { return (L == 64 && ROWS == 1 && MMAX == 8) ? 6 : 0; }
+
+template <int L, int ROWS, class RT, int NIT = 0>
 __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, const RhsBase& B,
                                          const RT (&w)[ROWS], const double (&u)[ROWS],
                                          const double (&du)[ROWS], double (&df)[ROWS],
-                                         const RhsLds<RT>& S, int lane) {
+                                         const RhsLds<RT>& S, int lane,
+                                         const ConcCache<NIT, RT>* cc = nullptr) {
   constexpr int LP = L * ROWS;
   const int ns = m.ns;
   const int sT = ns / L, lT = ns % L;
@@ -507,8 +524,9 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
   const double dinvRT = -dT * (B.invRT * invT1);
   char* rb = (char*)S.spc;
   lds_sync();
-#pragma unroll ROK4E_RX_UNROLL
-  for (int j = lane; j < m.nr; j += L) {
+  // one reaction: rate-constant increments, concentration products with increments,
+  // d q, scattered
+  auto diff_rx = [&](int j, const uint2 o, RT ca, RT cb, RT cc_, RT cd) {
     // the exponents' increments b dlnT - E d(1/RT); the mixed form reads b and E from
     // the FP32 table (half the bytes; its increments are FP32 anyway)
     double dlf, dlr;
@@ -525,18 +543,32 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
     const RT kf = kj.x, kr = kj.y;
     const RT dkf = kf * (RT)expm1_small(dlf);
     const RT dkr = kr * (RT)expm1_small(dlr);
-    const uint2 o = t.rxo[j];
-    const RT* a0 = (const RT*)(rb + (o.x & 0xFFFFu));
-    const RT* a1 = (const RT*)(rb + (o.x >> 16));
-    const RT* b0 = (const RT*)(rb + (o.y & 0xFFFFu));
-    const RT* b1 = (const RT*)(rb + (o.y >> 16));
+    const RT dca = *(const RT*)(rb + (o.x & 0xFFFFu) + LP * sizeof(RT));
+    const RT dcb = *(const RT*)(rb + (o.x >> 16) + LP * sizeof(RT));
+    const RT dcc = *(const RT*)(rb + (o.y & 0xFFFFu) + LP * sizeof(RT));
+    const RT dcd = *(const RT*)(rb + (o.y >> 16) + LP * sizeof(RT));
     // products of concentrations with increments: d(ab) = (a + da) db + da b
-    const RT ca = a0[0], dca = a0[LP], cb = a1[0], dcb = a1[LP];
     const RT pf = ca * cb, dpf = (ca + dca) * dcb + dca * cb;
-    const RT cc = b0[0], dcc = b0[LP], cd = b1[0], dcd = b1[LP];
-    const RT pr = cc * cd, dpr = (cc + dcc) * dcd + dcc * cd;
+    const RT pr = cc_ * cd, dpr = (cc_ + dcc) * dcd + dcc * cd;
     const RT dq = ((kf + dkf) * dpf + dkf * pf) - ((kr + dkr) * dpr + dkr * pr);
     scatter_rate<LP, RT>(rb, o, dq);
+  };
+  if constexpr (NIT > 0) {
+    if (cc) {
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int j = lane + it * L;
+        if (j < m.nr) diff_rx(j, t.rxo[j], cc->c[it][0], cc->c[it][1], cc->c[it][2], cc->c[it][3]);
+      }
+    }
+  }
+  if (NIT == 0 || !cc) {
+#pragma unroll ROK4E_RX_UNROLL
+    for (int j = lane; j < m.nr; j += L) {
+      const uint2 o = t.rxo[j];
+      diff_rx(j, o, *(const RT*)(rb + (o.x & 0xFFFFu)), *(const RT*)(rb + (o.x >> 16)),
+              *(const RT*)(rb + (o.y & 0xFFFFu)), *(const RT*)(rb + (o.y >> 16)));
+    }
   }
   lds_sync();
   double ph[ROWS];

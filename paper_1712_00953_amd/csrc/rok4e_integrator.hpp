@@ -80,13 +80,29 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
   for (int i = 0; i < ROWS; ++i) sq[i] = u[i] * u[i];
   const double delta = sqrt(P.eps_fd * (1.0 + sqrt(seg_sum<L, ROWS>(sq))));
   const double rdelta = 1.0 / delta;
+  // base concentrations of this lane's reactions, left in LDS by the base evaluation
+  constexpr int NIT = jvp_cache_iters<L, ROWS, MMAX>();
+  ConcCache<NIT, RT> cache;
+  const bool cached = NIT > 0 && m.nr <= NIT * L;
+  if constexpr (NIT > 0) {
+    const char* rb = (const char*)S.r.spc;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int j = lane + it * L;
+      const uint2 o = j < m.nr ? t.rxo[j] : make_uint2(0u, 0u);
+      cache.c[it][0] = *(const RT*)(rb + (o.x & 0xFFFFu));
+      cache.c[it][1] = *(const RT*)(rb + (o.x >> 16));
+      cache.c[it][2] = *(const RT*)(rb + (o.y & 0xFFFFu));
+      cache.c[it][3] = *(const RT*)(rb + (o.y >> 16));
+    }
+  }
 #pragma unroll
   for (int j = 0; j < MMAX; ++j) {
     if (j >= Meff) break;
     double du[ROWS], d[ROWS], wv[ROWS];
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) du[i] = delta * Q[i][j];
-    rhs_diff<L, ROWS, RT>(m, t, B, w, u, du, d, S.r, lane);
+    rhs_diff<L, ROWS, RT, NIT>(m, t, B, w, u, du, d, S.r, lane, cached ? &cache : nullptr);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) wv[i] = d[i] * rdelta;
     double hj[MMAX];
