@@ -299,6 +299,29 @@ def test_layouts_agree_and_runs_are_deterministic(R, orc):
         assert relative(outs[0], o) <= max(1e-10, 4 * env["env_rel"])
 
 
+def test_many_reactions_fall_back_to_lds_reads(R, orc):
+    """A 53-species mechanism with 450 reactions (more than the 384 the one-row layout
+    gathers per basis for its JVPs): the products read every concentration from LDS;
+    adaptive parity at the FP64 bar."""
+    mech = synth.make_mechanism(53, 450, 4, 1077, a_scale=A_SCALE)
+    st = synth.states_flame(mech, 16, 8, 2077)
+    M, dt, rtol, atol = 8, 1e-5, 1e-6, 1e-12
+
+    class W:
+        pass
+    w = W()
+    w.mech, w.M = mech, M
+    m = R.Mech(mech, M=M, max_attempts=MAX_ATT)
+    g = gpu_integrate(m, st, dt, rtol, atol)
+    o, env = envelope(orc, w, st, dt, rtol, atol, max_attempts=MAX_ATT)
+    d = dict(**env, **parity(g, o), rel=relative(g, o), mean_attempts=float((o[2] + o[3]).mean()))
+    _report("450 reactions", d)
+    assert np.all(g[4] == 0) and np.all(o[4] == 0)
+    assert d["rel"] <= max(1e-10, 4 * env["env_rel"])
+    assert d["match_frac"] >= match_floor(env["env_match"], st.n_cells)
+    m.close()
+
+
 @pytest.mark.parametrize("cfg,n", [(1, 300), (3, 512)])
 def test_per_attempt_schedule_is_bitwise_identical(R, cfg, n):
     """One launch per attempt with the cell state carried in device memory performs the
