@@ -69,6 +69,13 @@ extern "C" {
 #define ROK4E_METHOD_ROK4E 0
 #define ROK4E_METHOD_RKDP45 1
 
+/* Order in which the persistent schedule hands out cells (bitwise neutral: every cell's
+ * result is independent of it).  HOT_FIRST: by decreasing temperature, in bins of 16 K
+ * (cells with invalid T last), so that the cells that take the most attempts start
+ * first and the launch does not end on a few long cells; ARRAY: in array order. */
+#define ROK4E_ORDER_HOT_FIRST 0
+#define ROK4E_ORDER_ARRAY 1
+
 typedef struct rok4e_mech rok4e_mech;   /* opaque handle */
 
 /* Mechanism description; host arrays, copied to the device by rok4e_mech_create. */
@@ -100,7 +107,8 @@ typedef struct {
                              (bitwise neutral) */
   int32_t scheduling;     /* ROK4E_PERSISTENT or ROK4E_PER_ATTEMPT (bitwise neutral) */
   int32_t method;         /* ROK4E_METHOD_ROK4E (default) or ROK4E_METHOD_RKDP45 */
-  int32_t reserved;       /* 0 */
+  int32_t cell_order;     /* ROK4E_ORDER_HOT_FIRST (default) or ROK4E_ORDER_ARRAY (bitwise
+                             neutral; persistent schedule) */
   double h0;              /* first trial step; <= 0 means dt */
 } rok4e_options;
 

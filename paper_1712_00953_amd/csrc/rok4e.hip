@@ -21,6 +21,52 @@ namespace rok4e {
 
 __global__ void k_zero_u32(unsigned int* x) { *x = 0u; }
 
+// ---------------------------------------------------------- cell order ----
+// Hottest-first order of the persistent queue: a counting sort of the cells by
+// temperature bin (16 K wide, bin 0 the hottest; non-finite or non-positive T in the
+// last bin).  Within a bin the order is whatever the atomics give; the results do not
+// depend on it.
+constexpr int kOrderBins = 256;
+
+__device__ __forceinline__ int order_bin(double T) {
+  if (!(T > 0.0) || !__builtin_isfinite(T)) return kOrderBins - 1;
+  const int b = (int)((4096.0 - fmin(T, 4095.5)) * (1.0 / 16.0));
+  return b < 0 ? 0 : (b > kOrderBins - 1 ? kOrderBins - 1 : b);
+}
+
+__global__ void __launch_bounds__(256) k_fill_u32(unsigned int* x, int n, unsigned int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_order_hist(const double* T, int64_t n, unsigned int* bins) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&bins[order_bin(T[c])], 1u);
+}
+
+// Exclusive prefix sum of the kOrderBins counts in place (one block of kOrderBins threads).
+__global__ void __launch_bounds__(kOrderBins) k_order_scan(unsigned int* bins) {
+  __shared__ unsigned int s[kOrderBins];
+  const int i = threadIdx.x;
+  const unsigned int own = bins[i];
+  s[i] = own;
+  __syncthreads();
+  for (int d = 1; d < kOrderBins; d <<= 1) {
+    const unsigned int add = i >= d ? s[i - d] : 0u;
+    __syncthreads();
+    s[i] += add;
+    __syncthreads();
+  }
+  bins[i] = s[i] - own;
+}
+
+__global__ void __launch_bounds__(256) k_order_scatter(const double* T, int64_t n, unsigned int* bins,
+                                                       int32_t* order) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned int pos = atomicAdd(&bins[order_bin(T[c])], 1u);
+    order[pos] = (int32_t)c;
+  }
+}
+
 // Persistent integrator: every segment of L lanes pulls cells from a device counter
 // until the batch is exhausted, so cells with 1 and 1000 attempts share the chip
 // without waiting on each other.
@@ -44,8 +90,9 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m,
     // Every lane takes part in the atomic (the segment's first lane adds 1, the others
     // 0), so no lane-dependent branch surrounds the value that is then broadcast.
     const unsigned int ticket = atomicAdd(P.queue, lane == 0 ? 1u : 0u);
-    const int cell = seg_bcast<L>((int)ticket, 0);
-    if (cell < 0 || (int64_t)cell >= P.n_cells) break;
+    const int tk = seg_bcast<L>((int)ticket, 0);
+    if (tk < 0 || (int64_t)tk >= P.n_cells) break;
+    const int cell = P.order ? P.order[tk] : tk;
     double u[ROWS], s[ROWS], p;
     CellState c{};
     c.status = 3;
@@ -72,8 +119,9 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_rkdp(DevMech m, Laun
   init_seg<RT>(m, S);
   while (true) {
     const unsigned int ticket = atomicAdd(P.queue, lane == 0 ? 1u : 0u);
-    const int cell = seg_bcast<L>((int)ticket, 0);
-    if (cell < 0 || (int64_t)cell >= P.n_cells) break;
+    const int tk = seg_bcast<L>((int)ticket, 0);
+    if (tk < 0 || (int64_t)tk >= P.n_cells) break;
+    const int cell = P.order ? P.order[tk] : tk;
     double u[ROWS], s[ROWS], p;
     CellState c{};
     c.status = 3;
@@ -301,6 +349,8 @@ struct rok4e_mech {
   int32_t* d_acc = nullptr;
   int32_t* d_rej = nullptr;
   int32_t* d_status = nullptr;
+  int32_t* d_order = nullptr;      // [cap] queue order of the persistent schedule
+  unsigned int* d_bins = nullptr;  // [kOrderBins] temperature-bin counts / offsets
   int64_t last_n = 0;
   // per-attempt schedule: carried cell state, active lists and their counters
   int64_t att_cap = 0;
@@ -327,6 +377,7 @@ bool options_ok(const rok4e_options& o) {
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return false;
   if (o.scheduling != ROK4E_PERSISTENT && o.scheduling != ROK4E_PER_ATTEMPT) return false;
   if (o.method != ROK4E_METHOD_ROK4E && o.method != ROK4E_METHOD_RKDP45) return false;
+  if (o.cell_order != ROK4E_ORDER_HOT_FIRST && o.cell_order != ROK4E_ORDER_ARRAY) return false;
   if (!std::isfinite(o.h0)) return false;
   return true;
 }
@@ -525,6 +576,20 @@ int ensure_workspace(rok4e_mech* m, int64_t n, hipStream_t stream) {
   return rok4e_reserve(m, n);
 }
 
+// Queue order of the persistent schedule (hottest first unless the options ask for
+// array order): four small kernels on the launch stream, none of them a memset, so a
+// captured launch replays them too.  Sets P.order.
+void launch_order(rok4e_mech* m, const double* T, int64_t n, hipStream_t st, Launch& P) {
+  P.order = nullptr;
+  if (m->opt.cell_order != ROK4E_ORDER_HOT_FIRST || n <= 1) return;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)m->cu_count * 8);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, m->d_bins, kOrderBins, 0u);
+  hipLaunchKernelGGL(k_order_hist, dim3(grid), dim3(256), 0, st, T, n, m->d_bins);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, st, m->d_bins);
+  hipLaunchKernelGGL(k_order_scatter, dim3(grid), dim3(256), 0, st, T, n, m->d_bins, m->d_order);
+  P.order = m->d_order;
+}
+
 int check_state_args(int64_t n, rok4e_mech* mech, const void* Y, const void* T, const void* p) {
   if (!mech || n < 0) return ROK4E_EINVAL;
   if (n > 0 && (!Y || !T || !p)) return ROK4E_EINVAL;
@@ -619,7 +684,8 @@ int rok4e_mech_destroy(rok4e_mech* m) {
   (void)hipGetDevice(&dev);
   (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
-  void* bufs[] = {m->d_image, m->d_queue, m->d_acc, m->d_rej, m->d_status, m->d_st, m->d_fnq, m->d_H,
+  void* bufs[] = {m->d_image, m->d_queue, m->d_acc, m->d_rej, m->d_status, m->d_order, m->d_bins,
+                  m->d_st, m->d_fnq, m->d_H,
                   m->d_act[0], m->d_act[1], m->d_cnt};
   for (void* b : bufs) (void)hipFree(b);
   if (m->h_cnt) (void)hipHostFree(m->h_cnt);
@@ -715,11 +781,14 @@ int rok4e_reserve(rok4e_mech* m, int64_t max_cells) {
   (void)hipFree(m->d_acc);
   (void)hipFree(m->d_rej);
   (void)hipFree(m->d_status);
-  m->d_acc = m->d_rej = m->d_status = nullptr;
+  (void)hipFree(m->d_order);
+  m->d_acc = m->d_rej = m->d_status = m->d_order = nullptr;
   m->cap = 0;
   hipError_t e = hipMalloc((void**)&m->d_acc, max_cells * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc((void**)&m->d_rej, max_cells * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc((void**)&m->d_status, max_cells * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_order, max_cells * sizeof(int32_t));
+  if (e == hipSuccess && !m->d_bins) e = hipMalloc((void**)&m->d_bins, kOrderBins * sizeof(unsigned int));
   if (e != hipSuccess) return hip_fail(e);
   m->cap = max_cells;
   return ROK4E_OK;
@@ -748,6 +817,7 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
     if (m->opt.scheduling != ROK4E_PERSISTENT) return ROK4E_ENOTSUP;
     rc = shape_for(m, sl, n_cells, (const void*)m->var->rkdp, true, &sh);
     if (rc) return rc;
+    launch_order(m, T, n_cells, st, P);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
     hipLaunchKernelGGL(m->var->rkdp, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
     const hipError_t e = hipGetLastError();
@@ -768,6 +838,7 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
   }
   rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate, true, &sh);
   if (rc) return rc;
+  launch_order(m, T, n_cells, st, P);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
   hipLaunchKernelGGL(m->var->integrate, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
   const hipError_t e = hipGetLastError();

@@ -84,6 +84,7 @@ struct Launch {
   unsigned int* queue;
   int32_t* acc; int32_t* rej; int32_t* status;
   double* hio;   // [n] per-cell first trial step in, step for the next call out (or null)
+  const int32_t* order;   // [n] cell handed out for each queue ticket (or null: array order)
   int seg_bytes, off_k, off_H, off_LU, off_rdiag;
 };
 

@@ -22,6 +22,7 @@ FP64, MIXED = 0, 1
 PERSISTENT, PER_ATTEMPT = 0, 1
 SPLIT_SIMPLER, SPLIT_STRANG = 0, 1
 METHOD_ROK4E, METHOD_RKDP45 = 0, 1
+ORDER_HOT_FIRST, ORDER_ARRAY = 0, 1
 CELL_OK, CELL_MAX_ATTEMPTS, CELL_STEP_UNDERFLOW, CELL_BAD_INPUT = 0, 1, 2, 3
 
 EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "rok4e_set_options",
@@ -44,7 +45,7 @@ class Options(C.Structure):
     _fields_ = [("M", C.c_int32), ("precision", C.c_int32), ("max_attempts", C.c_int32),
                 ("fixed_steps", C.c_int32), ("lanes_per_cell", C.c_int32),
                 ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("scheduling", C.c_int32), ("method", C.c_int32), ("reserved", C.c_int32),
+                ("scheduling", C.c_int32), ("method", C.c_int32), ("cell_order", C.c_int32),
                 ("h0", C.c_double)]
 
 
@@ -125,9 +126,10 @@ def _check(rc, what):
 
 def options(M=4, precision=FP64, max_attempts=0, fixed_steps=0, lanes_per_cell=0,
             waves_per_block=0, blocks_per_cu=0, scheduling=PERSISTENT, method=METHOD_ROK4E,
-            h0=0.0) -> Options:
+            h0=0.0, cell_order=None) -> Options:
+    order = ORDER_HOT_FIRST if cell_order is None else int(cell_order)
     return Options(int(M), int(precision), int(max_attempts), int(fixed_steps), int(lanes_per_cell),
-                   int(waves_per_block), int(blocks_per_cu), int(scheduling), int(method), 0, float(h0))
+                   int(waves_per_block), int(blocks_per_cu), int(scheduling), int(method), order, float(h0))
 
 
 def _ptr(t):

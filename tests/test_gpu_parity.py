@@ -325,8 +325,9 @@ def test_many_reactions_fall_back_to_lds_reads(R, orc):
 @pytest.mark.parametrize("cfg,n", [(1, 300), (3, 512)])
 def test_per_attempt_schedule_is_bitwise_identical(R, cfg, n):
     """One launch per attempt with the cell state carried in device memory performs the
-    same arithmetic as the persistent kernel: identical states and counts, also for an
-    invalid cell, the attempt limit and fixed steps."""
+    same arithmetic as the persistent kernel, and the persistent queue's order (hottest
+    cells first, or array order) does not touch a cell's arithmetic: identical states and
+    counts, also for an invalid cell, the attempt limit and fixed steps."""
     w = synth.workload(cfg, a_scale=A_SCALE)
     idx = synth.stratified_sample(w.states.T, n, 300 + cfg)
     st = w.states.subset(idx)
@@ -335,13 +336,15 @@ def test_per_attempt_schedule_is_bitwise_identical(R, cfg, n):
     st = synth.States(st.Y, T, st.p)
     for kw in (dict(max_attempts=MAX_ATT), dict(max_attempts=3), dict(fixed_steps=2)):
         outs = []
-        for sched in (R.PERSISTENT, R.PER_ATTEMPT):
-            m = R.Mech(w.mech, M=w.M, scheduling=sched, **kw)
+        for sched, order in ((R.PERSISTENT, R.ORDER_HOT_FIRST), (R.PERSISTENT, R.ORDER_ARRAY),
+                             (R.PER_ATTEMPT, R.ORDER_HOT_FIRST)):
+            m = R.Mech(w.mech, M=w.M, scheduling=sched, cell_order=order, **kw)
             outs.append(gpu_integrate(m, st, w.dt, w.rtol, w.atol))
             m.close()
         assert outs[0][4][3] == 3
-        for a, b in zip(*outs):
-            np.testing.assert_array_equal(a, b)
+        for other in outs[1:]:
+            for a, b in zip(outs[0], other):
+                np.testing.assert_array_equal(a, b)
 
 
 def test_graph_capture_replays_match_eager(R):
