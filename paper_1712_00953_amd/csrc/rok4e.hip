@@ -578,10 +578,12 @@ int ensure_workspace(rok4e_mech* m, int64_t n, hipStream_t stream) {
 
 // Queue order of the persistent schedule (hottest first unless the options ask for
 // array order): four small kernels on the launch stream, none of them a memset, so a
-// captured launch replays them too.  Sets P.order.
-void launch_order(rok4e_mech* m, const double* T, int64_t n, hipStream_t st, Launch& P) {
+// captured launch replays them too.  Sets P.order.  Skipped for batches of fewer than
+// eight cells per segment in flight, where most cells start at once and the order
+// cannot shorten the tail by more than the kernels cost.
+void launch_order(rok4e_mech* m, const double* T, int64_t n, int64_t segments, hipStream_t st, Launch& P) {
   P.order = nullptr;
-  if (m->opt.cell_order != ROK4E_ORDER_HOT_FIRST || n <= 1) return;
+  if (m->opt.cell_order != ROK4E_ORDER_HOT_FIRST || n < 8 * segments) return;
   const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)m->cu_count * 8);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, m->d_bins, kOrderBins, 0u);
   hipLaunchKernelGGL(k_order_hist, dim3(grid), dim3(256), 0, st, T, n, m->d_bins);
@@ -817,7 +819,7 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
     if (m->opt.scheduling != ROK4E_PERSISTENT) return ROK4E_ENOTSUP;
     rc = shape_for(m, sl, n_cells, (const void*)m->var->rkdp, true, &sh);
     if (rc) return rc;
-    launch_order(m, T, n_cells, st, P);
+    launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
     hipLaunchKernelGGL(m->var->rkdp, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
     const hipError_t e = hipGetLastError();
@@ -838,7 +840,7 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
   }
   rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate, true, &sh);
   if (rc) return rc;
-  launch_order(m, T, n_cells, st, P);
+  launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
   hipLaunchKernelGGL(m->var->integrate, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
   const hipError_t e = hipGetLastError();

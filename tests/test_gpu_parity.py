@@ -347,12 +347,34 @@ def test_per_attempt_schedule_is_bitwise_identical(R, cfg, n):
                 np.testing.assert_array_equal(a, b)
 
 
-def test_graph_capture_replays_match_eager(R):
-    """The persistent launch (queue reset kernel + integrator, no memset node) captured
-    in a HIP graph: several replays, each on fresh inputs copied in eagerly between them,
+def test_cell_order_is_bitwise_neutral(R):
+    """A batch large enough for the persistent queue to be ordered (32,768 cells of the
+    53-species flame slice, more than eight per segment in flight; one invalid cell):
+    hottest-first and array order give identical states and counts, and the ordered
+    launch visits every cell once."""
+    w = synth.workload(2, a_scale=A_SCALE)
+    st = w.states.subset(np.arange(32768))
+    T = st.T.copy()
+    T[5] = np.nan
+    st = synth.States(st.Y, T, st.p)
+    outs = []
+    for order in (R.ORDER_HOT_FIRST, R.ORDER_ARRAY):
+        m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT, cell_order=order)
+        outs.append(gpu_integrate(m, st, w.dt, w.rtol, w.atol))
+        m.close()
+    assert outs[0][4][5] == 3 and np.sum(outs[0][4] == 0) == st.n_cells - 1
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("n", [400, 32768])
+def test_graph_capture_replays_match_eager(R, n):
+    """The persistent launch (queue reset kernel + integrator, no memset node; for the
+    larger batch also the four kernels that order the queue hottest first) captured in a
+    HIP graph: several replays, each on fresh inputs copied in eagerly between them,
     equal the eager call bit for bit."""
     import torch
-    w = synth.workload(1, a_scale=A_SCALE, n_cells=400)
+    w = synth.workload(1, a_scale=A_SCALE, n_cells=n)
     st = w.states
     m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
     m.reserve(st.n_cells)
