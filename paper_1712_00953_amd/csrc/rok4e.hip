@@ -81,7 +81,7 @@ constexpr int occupancy() { return ROWS == 1 ? ROK4E_OCC_ROWS1 : 2; }
 template <int L, int ROWS, int MMAX, class RT>
 __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m, Launch P) {
   extern __shared__ __align__(16) char smem[];
-  const MechLds t = load_mech_lds(m, smem);
+  const MechLds t = load_mech_lds<L>(m, smem);
   const int lane = (int)(threadIdx.x % L);
   char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
   const SegLds<RT> S = seg_lds<RT>(seg, P);
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m,
 template <int L, int ROWS, class RT>
 __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_rkdp(DevMech m, Launch P) {
   extern __shared__ __align__(16) char smem[];
-  const MechLds t = load_mech_lds(m, smem);
+  const MechLds t = load_mech_lds<L>(m, smem);
   const int lane = (int)(threadIdx.x % L);
   char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
   const SegLds<RT> S = seg_lds<RT>(seg, P);
@@ -155,7 +155,7 @@ struct AttemptWork {
 template <int L, int ROWS, int MMAX, class RT>
 __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_attempt(DevMech m, Launch P, AttemptWork W) {
   extern __shared__ __align__(16) char smem[];
-  const MechLds t = load_mech_lds(m, smem);
+  const MechLds t = load_mech_lds<L>(m, smem);
   const int lane = (int)(threadIdx.x % L);
   char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
   const SegLds<RT> S = seg_lds<RT>(seg, P);
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_attempt(DevMech m, L
 template <int L, int ROWS, class RT>
 __global__ void __launch_bounds__(256, 2) k_rhs(DevMech m, Launch P, double* dY, double* dT) {
   extern __shared__ __align__(16) char smem[];
-  const MechLds t = load_mech_lds(m, smem);
+  const MechLds t = load_mech_lds<L>(m, smem);
   const int lane = (int)(threadIdx.x % L);
   char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
   const SegLds<RT> S = seg_lds<RT>(seg, P);
@@ -252,7 +252,7 @@ template <int L, int ROWS, int MMAX, class RT>
 __global__ void __launch_bounds__(256, 2) k_arnoldi(DevMech m, Launch P, double* Qo, double* Ho,
                                                   int32_t* Mo) {
   extern __shared__ __align__(16) char smem[];
-  const MechLds t = load_mech_lds(m, smem);
+  const MechLds t = load_mech_lds<L>(m, smem);
   const int lane = (int)(threadIdx.x % L);
   char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
   const SegLds<RT> S = seg_lds<RT>(seg, P);

@@ -68,6 +68,11 @@ struct MechLds {
   const uint2* rxo;
   const int* spos;
   const float4* bE32;   // (b_f, E_f, b_r, E_r) in FP32, mixed-precision images only
+  // this lane's state row (lane % L) of W, 1/W, cp, hf and the species position, read
+  // once at kernel start: the one-row layouts take them from registers (or private
+  // memory) instead of LDS in every evaluation
+  double rW, rinvW, rcp, rhf;
+  int rspos;
 };
 
 // A pair of rate-type values (the forward and reverse rate constants of a reaction).
@@ -90,6 +95,7 @@ struct Launch {
 
 // Copies the table image to the start of the block's LDS and returns the view.  All
 // threads of the block take part; ends with a block barrier (kernel start only).
+template <int L>
 __device__ __forceinline__ MechLds load_mech_lds(const DevMech& m, char* lds) {
   int4* dst = (int4*)lds;
   for (int i = threadIdx.x; i < m.image_bytes / 16; i += blockDim.x) dst[i] = m.image[i];
@@ -103,6 +109,8 @@ __device__ __forceinline__ MechLds load_mech_lds(const DevMech& m, char* lds) {
   t.rxo = (const uint2*)(lds + m.off_rxo);
   t.spos = (const int*)(lds + m.off_spos);
   t.bE32 = m.off_bE32 ? (const float4*)(lds + m.off_bE32) : nullptr;
+  const int r0 = (int)(threadIdx.x % L);
+  t.rW = t.W[r0]; t.rinvW = t.invW[r0]; t.rcp = t.cp[r0]; t.rhf = t.hf[r0]; t.rspos = t.spos[r0];
   return t;
 }
 
@@ -410,8 +418,8 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;          // rows past the species have invW = cp = 0
-    sc2[s][0] = (r < ns ? u[s] : 0.0) * t.invW[r];
-    sc2[s][1] = (r < ns ? u[s] : 0.0) * t.cp[r];
+    sc2[s][0] = (r < ns ? u[s] : 0.0) * (ROWS == 1 ? t.rinvW : t.invW[r]);
+    sc2[s][1] = (r < ns ? u[s] : 0.0) * (ROWS == 1 ? t.rcp : t.cp[r]);
   }
   seg_sum_rows_k<L, ROWS, 2>(sc2, sums);
   const double sigma = sums[0], cpbar = sums[1];
@@ -421,8 +429,8 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
     if (r < ns) {
-      const int q = t.spos[r];
-      S.spc[q] = (RT)(1e-6 * rho * u[s] * t.invW[r]);
+      const int q = (ROWS == 1 ? t.rspos : t.spos[r]);
+      S.spc[q] = (RT)(1e-6 * rho * u[s] * (ROWS == 1 ? t.rinvW : t.invW[r]));
       *acc_at<LP, RT>((char*)S.spc, q * sizeof(RT)) = 0.0;
     }
   }
@@ -447,11 +455,11 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const RT wk = r < ns ? (RT)(1e6 * *acc_at<LP, RT>((char*)S.spc, t.spos[r] * sizeof(RT))) : (RT)0;
+    const RT wk = r < ns ? (RT)(1e6 * *acc_at<LP, RT>((char*)S.spc, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(RT))) : (RT)0;
     w[s] = wk;
-    f[s] = (double)((RT)t.W[r] * wk * (RT)invrho);
-    const RT hk = (RT)(t.hf[r] + t.cp[r] * (T - kTref));
-    ph[s] = (double)(hk * (RT)t.W[r] * wk);
+    f[s] = (double)((RT)(ROWS == 1 ? t.rW : t.W[r]) * wk * (RT)invrho);
+    const RT hk = (RT)((ROWS == 1 ? t.rhf : t.hf[r]) + (ROWS == 1 ? t.rcp : t.cp[r]) * (T - kTref));
+    ph[s] = (double)(hk * (RT)(ROWS == 1 ? t.rW : t.W[r]) * wk);
   }
   const double hsum = seg_sum<L, ROWS>(ph);
   const double invD = rcp(rho * cpbar);
@@ -501,8 +509,8 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    sc2[s][0] = (r < ns ? du[s] : 0.0) * t.invW[r];
-    sc2[s][1] = (r < ns ? du[s] : 0.0) * t.cp[r];
+    sc2[s][0] = (r < ns ? du[s] : 0.0) * (ROWS == 1 ? t.rinvW : t.invW[r]);
+    sc2[s][1] = (r < ns ? du[s] : 0.0) * (ROWS == 1 ? t.rcp : t.cp[r]);
   }
   seg_sum_rows_k<L, ROWS, 2>(sc2, sums);
   const double dsigma = sums[0], dcp = sums[1];
@@ -516,8 +524,8 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
     if (r < ns) {
-      const int q = t.spos[r];
-      S.spc[LP + q] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * t.invW[r]);
+      const int q = (ROWS == 1 ? t.rspos : t.spos[r]);
+      S.spc[LP + q] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * (ROWS == 1 ? t.rinvW : t.invW[r]));
       *acc_at<LP, RT>((char*)S.spc, q * sizeof(RT)) = 0.0;
     }
   }
@@ -576,11 +584,11 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const double dw = r < ns ? 1e6 * *acc_at<LP, RT>((char*)S.spc, t.spos[r] * sizeof(RT)) : 0.0;
+    const double dw = r < ns ? 1e6 * *acc_at<LP, RT>((char*)S.spc, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(RT)) : 0.0;
     const double wk = (double)w[s];
-    df[s] = t.W[r] * (dw * invrho1 - wk * drho * B.invrho * invrho1);
-    const double hk = t.hf[r] + t.cp[r] * (T - kTref), dhk = t.cp[r] * dT;
-    ph[s] = t.W[r] * ((hk + dhk) * dw + dhk * wk);
+    df[s] = (ROWS == 1 ? t.rW : t.W[r]) * (dw * invrho1 - wk * drho * B.invrho * invrho1);
+    const double hk = (ROWS == 1 ? t.rhf : t.hf[r]) + (ROWS == 1 ? t.rcp : t.cp[r]) * (T - kTref), dhk = (ROWS == 1 ? t.rcp : t.cp[r]) * dT;
+    ph[s] = (ROWS == 1 ? t.rW : t.W[r]) * ((hk + dhk) * dw + dhk * wk);
   }
   const double dhsum = seg_sum<L, ROWS>(ph);
   const double D = rho * B.cpbar, dD = drho * cp1 + rho * dcp;
