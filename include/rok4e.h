@@ -72,7 +72,8 @@ extern "C" {
 /* Order in which the persistent schedule hands out cells (bitwise neutral: every cell's
  * result is independent of it).  HOT_FIRST: by decreasing temperature, in bins of 16 K
  * (cells with invalid T last), so that the cells that take the most attempts start
- * first and the launch does not end on a few long cells; ARRAY: in array order. */
+ * first and the launch does not end on a few long cells; batches of fewer than eight
+ * cells per segment in flight keep array order.  ARRAY: in array order. */
 #define ROK4E_ORDER_HOT_FIRST 0
 #define ROK4E_ORDER_ARRAY 1
 
