@@ -111,6 +111,9 @@ def grid(nx, ny, nz, dx, vel, diff) -> Grid:
 
 def transport(g: Grid, n_species, Y, T, S, stream=None):
     """rok4e_transport: S[r * n + c] = T(U)_r for the state (Y, T) on grid g."""
+    n = int(g.nx) * int(g.ny) * int(g.nz)
+    for t, cnt, name in ((Y, int(n_species) * n, "Y"), (T, n, "T"), (S, (int(n_species) + 1) * n, "S")):
+        _need(t, cnt, name)
     _check(load().rok4e_transport(C.byref(g), int(n_species), _ptr(Y), _ptr(T), _ptr(S), _stream(stream)),
            "rok4e_transport")
 
@@ -140,16 +143,18 @@ def _ptr(t):
     return C.c_void_p(int(t))
 
 
-def _need(t, count, name):
-    """Host-side check of a device operand before its pointer goes to a kernel: float64,
-    contiguous, on a GPU, at least count elements (the kernels index it up to there)."""
+def _need(t, count, name, dtype="float64"):
+    """Host-side check of a device operand before its pointer goes to a kernel: of the
+    given dtype, contiguous, on a GPU, at least count elements (the kernels index it up
+    to there)."""
     if t is None:
         return
     if not hasattr(t, "data_ptr"):
         raise TypeError(f"{name}: expected a device tensor")
     import torch
-    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() < count:
-        raise ValueError(f"{name}: need a contiguous float64 device tensor with >= {count} elements, "
+    want = getattr(torch, dtype)
+    if t.dtype != want or not t.is_cuda or not t.is_contiguous() or t.numel() < count:
+        raise ValueError(f"{name}: need a contiguous {dtype} device tensor with >= {count} elements, "
                          f"got {t.dtype} {tuple(t.shape)} on {t.device}")
 
 
@@ -224,6 +229,8 @@ class Mech:
         """rok4e_tune: picks the fastest waves-per-block on a copy of this batch; returns
         (waves_per_block, ms)."""
         n = int(T.shape[0])
+        for t, cnt, name in ((Y, self.n_species * n, "Y"), (T, n, "T"), (p, n, "p")):
+            _need(t, cnt, name)
         wv, ms = C.c_int32(0), C.c_float(0.0)
         _check(load().rok4e_tune(n, self._h, _ptr(Y), _ptr(T), _ptr(p), float(dt), float(rtol), float(atol),
                                  C.byref(wv), C.byref(ms), _stream(stream)), "rok4e_tune")
@@ -232,11 +239,19 @@ class Mech:
 
     def rhs(self, Y, T, p, dY, dT, stream=None):
         n = int(T.shape[0])
+        ns = self.n_species
+        for t, cnt, name in ((Y, ns * n, "Y"), (T, n, "T"), (p, n, "p"), (dY, ns * n, "dY"), (dT, n, "dT")):
+            _need(t, cnt, name)
         _check(load().rok4e_rhs(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(dY), _ptr(dT), _stream(stream)),
                "rok4e_rhs")
 
     def arnoldi(self, Y, T, p, Q, H, Meff, stream=None):
         n = int(T.shape[0])
+        ns, M = self.n_species, int(self.opts.M)
+        for t, cnt, name in ((Y, ns * n, "Y"), (T, n, "T"), (p, n, "p"), (Q, n * M * (ns + 1), "Q"),
+                             (H, n * M * M, "H")):
+            _need(t, cnt, name)
+        _need(Meff, n, "Meff", "int32")
         _check(load().rok4e_arnoldi(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(Q), _ptr(H), _ptr(Meff),
                                     _stream(stream)), "rok4e_arnoldi")
 
@@ -244,6 +259,9 @@ class Mech:
         """rok4e_split_step: one Simpler (or Strang) step of size h on the grid, in place.
         work: a device tensor of at least workspace_bytes(grid) bytes."""
         n = int(grid.nx) * int(grid.ny) * int(grid.nz)
+        ns = self.n_species
+        for t, cnt, name in ((Y, ns * n, "Y"), (T, n, "T"), (p, n, "p"), (src, (ns + 1) * n, "src")):
+            _need(t, cnt, name)
         _check(load().rok4e_split_step(self._h, C.byref(grid), int(scheme), _ptr(Y), _ptr(T), _ptr(p), _ptr(src),
                                        float(h), float(rtol), float(atol), int(nsub), _ptr(work),
                                        int(work.numel() * work.element_size()), _stream(stream)),
