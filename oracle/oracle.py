@@ -274,3 +274,87 @@ def row_dense_cell(mech, u, p, dt, nsteps, jvp=JVP_COMPLEX):
     if rc != 0:
         raise RuntimeError(f"row_dense_cell failed: {rc}")
     return u
+
+
+# ------------------------------------------------ conservative variables (Sec. 5) ----
+
+def cons_state(mech, Y, T, p, vel):
+    """Conservative variables [(ns+5), n] (rho Y_k, rho, rho u_x, rho u_y, rho u_z, rho E)
+    of the states (Y, T, p) moving with velocity vel [3, n]: ideal gas rho = p / (Ru T
+    sum Y_k/W_k), internal energy e = sum_k Y_k (h_k - Ru T / W_k) with
+    h_k = h_f,k + c_p,k (T - 298.15), E = e + |vel|^2 / 2."""
+    Ru = 8.314462618
+    W = np.asarray(mech.W, np.float64)[:, None]
+    cp = np.asarray(mech.cp, np.float64)[:, None]
+    hf = np.asarray(mech.hf, np.float64)[:, None]
+    Y = np.asarray(Y, np.float64)
+    T = np.asarray(T, np.float64)
+    vel = np.asarray(vel, np.float64)
+    rho = np.asarray(p, np.float64) / (Ru * T * (Y / W).sum(0))
+    e = (Y * (hf + cp * (T - 298.15) - Ru * T / W)).sum(0)
+    E = e + 0.5 * (vel * vel).sum(0)
+    return np.ascontiguousarray(np.vstack([rho * Y, rho[None], rho * vel, (rho * E)[None]]))
+
+
+def cons_temperature(mech, U):
+    """Temperature of the conservative variables of every cell (NaN where rho c_v <= 0)."""
+    h = MechHandle(mech)
+    U = np.ascontiguousarray(U, np.float64)
+    n = U.shape[1]
+    T = np.zeros(n)
+    lib().orc_cons_temperature(C.byref(h.s), C.c_int64(n), _p(U), _p(T))
+    return T
+
+
+def cons_f(mech, u, s=None):
+    """f of one cell in the auxiliary-temperature state u (length ns+6)."""
+    h = MechHandle(mech)
+    u = np.ascontiguousarray(u, np.float64)
+    s = None if s is None else np.ascontiguousarray(s, np.float64)
+    out = np.zeros_like(u)
+    lib().orc_cons_f(C.byref(h.s), _p(u), _p(s), _p(out))
+    return out
+
+
+def cons_fdiff(mech, u, du, s=None, quad=False):
+    """f(u + du) - f(u) of one auxiliary-temperature cell: difference form, or the
+    quad-precision reference."""
+    h = MechHandle(mech)
+    u = np.ascontiguousarray(u, np.float64)
+    du = np.ascontiguousarray(du, np.float64)
+    s = None if s is None else np.ascontiguousarray(s, np.float64)
+    out = np.zeros_like(u)
+    lib().orc_cons_fdiff(C.byref(h.s), _p(u), _p(s), _p(du), C.c_int(1 if quad else 0), _p(out))
+    return out
+
+
+def cons_jvp(mech, u, v, s=None, mode=JVP_FD):
+    """J(u) v of one auxiliary-temperature cell (FD in difference form, or complex step)."""
+    h = MechHandle(mech)
+    u = np.ascontiguousarray(u, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    s = None if s is None else np.ascontiguousarray(s, np.float64)
+    out = np.zeros_like(u)
+    if lib().orc_cons_jvp(C.byref(h.s), _p(u), _p(s), _p(v), C.c_int(mode), _p(out)) != 0:
+        raise RuntimeError("jvp mode not available")
+    return out
+
+
+def integrate_cons(mech, U, dt, rtol, atol, M, S=None, jvp=JVP_FD, fixed_steps=0,
+                   max_attempts=0, nthreads=0, fma=False):
+    """Reaction substep in conservative variables with the auxiliary temperature over
+    [0, dt]; returns (U, T_aux, accepted, rejected, status) as new arrays.  T_aux is NaN
+    for cells with invalid input."""
+    h = MechHandle(mech)
+    U = np.array(U, np.float64, order="C", copy=True)
+    S = None if S is None else np.ascontiguousarray(S, np.float64)
+    n = U.shape[1]
+    Ta = np.full(n, np.nan)
+    acc = np.zeros(n, np.int32)
+    rej = np.zeros(n, np.int32)
+    st = np.zeros(n, np.int32)
+    o = make_opts(M, jvp, fixed_steps, max_attempts, 0.0, 0.0)
+    lib(fma).orc_integrate_cons(C.byref(h.s), C.byref(o), C.c_int64(n), _p(U), _p(S), C.c_double(dt),
+                                C.c_double(rtol), C.c_double(atol), _p(Ta), _p(acc), _p(rej), _p(st),
+                                C.c_int(nthreads))
+    return U, Ta, acc, rej, st

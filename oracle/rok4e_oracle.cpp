@@ -40,6 +40,10 @@
 //     the proposal made before the last step was shortened to end at dt).
 // Also here, for the efficiency study of Sec. 5: the explicit Dormand-Prince 5(4) pair
 // (published tableau, first-same-as-last, the same error norm, elementary controller).
+// And the reaction substep in the conservative variables of a compressible solver with
+// the auxiliary temperature equation (Sec. 5, e:chemical_source_balanced and
+// e:aux_t_equation; ConsProblem), reading the species energy there as the internal
+// energy e_k = h_k - Ru T / W_k.
 //
 // Built with -O2 -fno-fast-math -ffp-contract=off so each operation rounds once.
 
@@ -248,6 +252,159 @@ struct CellProblem {
     out[ns] = -(dhsum / (D + dD) - hsum * dD / (D * (D + dD)));
   }
 };
+
+// Net production rates wdot_k = sum_j nu_kj q_j (mol/(cm^3 s)) of the mass-action
+// mechanism at concentrations c (mol/cm^3) and temperature T, reactions in index order.
+template <class S>
+void net_rates(const orc_mech* m, const S* c, S T, S* wdot) {
+  const int ns = m->n_species, nr = m->n_reactions;
+  for (int k = 0; k < ns; ++k) wdot[k] = S(0.0);
+  const S lnT = log_(T);
+  const S invRT = S(1.0) / (S(kRu) * T);
+  for (int j = 0; j < nr; ++j) {
+    const S kf = exp_(S(m->lnAf[j]) + S(m->bf[j]) * lnT - S(m->Ef[j]) * invRT);
+    const S kr = exp_(S(m->lnAr[j]) + S(m->br[j]) * lnT - S(m->Er[j]) * invRT);
+    S pf = 1.0, pr = 1.0;
+    for (int a = 0; a < 2; ++a) {
+      if (m->reac[2 * j + a] >= 0) pf = pf * c[m->reac[2 * j + a]];
+      if (m->prod[2 * j + a] >= 0) pr = pr * c[m->prod[2 * j + a]];
+    }
+    const S q = kf * pf - kr * pr;
+    for (int a = 0; a < 2; ++a) {
+      if (m->reac[2 * j + a] >= 0) wdot[m->reac[2 * j + a]] -= q;
+      if (m->prod[2 * j + a] >= 0) wdot[m->prod[2 * j + a]] += q;
+    }
+  }
+}
+
+// One cell in the conservative variables of a compressible flow solver, with the
+// auxiliary temperature of Sec. 5 (e:chemical_source_balanced, e:aux_t_equation):
+//   u = (rho Y_1 .. rho Y_ns, T, rho, rho u_x, rho u_y, rho u_z, rho E),  n = ns + 6.
+// The chemistry changes only the rho Y_k (constant-volume reactor: c_k = rho Y_k / W_k);
+// every conservative row also receives its balancing constant s (the transport term of
+// the previous step; s may be null, its T entry is not used).  The temperature source is
+//   dT/dt = ( -sum_k e_k F_k + |v|^2/2 F_rho - v . F_m + F_E ) / (rho c_v),
+// F the forced derivatives of the conservative rows, v = (rho u) / rho.
+// Reading: the species energy of e:aux_t_equation is the mass-specific internal energy
+// e_k = h_k - Ru T / W_k (h_k = h_f,k + c_p,k (T - T_ref)), and rho c_v = sum_k rho Y_k
+// (c_p,k - Ru / W_k).  With it the auxiliary temperature equals the temperature of the
+// conservative variables along the exact solution, the property Sec. 5 states; with
+// the enthalpy it would not.
+struct ConsProblem {
+  static constexpr bool kComplex = true;
+  static constexpr bool kDiff = true;
+  const orc_mech* m;
+  const double* s;   // may be null
+  int n() const { return m->n_species + 6; }
+
+  double srow(int i) const { return s ? s[i] : 0.0; }
+
+  template <class S>
+  void f(const S* u, S* out) const {
+    const int ns = m->n_species;
+    const S T = u[ns], rho = u[ns + 1];
+    std::vector<S> c(ns), wdot(ns);
+    for (int k = 0; k < ns; ++k) c[k] = S(1e-6) * u[k] / S(m->W[k]);   // mol/cm^3
+    net_rates<S>(m, c.data(), T, wdot.data());
+    S esum = 0.0, D = 0.0;
+    for (int k = 0; k < ns; ++k) {
+      out[k] = S(m->W[k]) * (S(1e6) * wdot[k]) + S(srow(k));           // kg/(m^3 s)
+      const S ek = S(m->hf[k]) + S(m->cp[k]) * (T - S(kTref)) - S(kRu) * T / S(m->W[k]);
+      esum += ek * out[k];
+      D += u[k] * (S(m->cp[k]) - S(kRu) / S(m->W[k]));
+    }
+    for (int i = 1; i <= 5; ++i) out[ns + i] = S(srow(ns + i));
+    S ke = 0.0, vF = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const S v = u[ns + 2 + d] / rho;
+      ke += v * v;
+      vF += v * out[ns + 2 + d];
+    }
+    out[ns] = (-esum + S(0.5) * ke * out[ns + 1] - vF + out[ns + 5]) / D;
+  }
+
+  // out = f(u + du) - f(u) in difference form (every quantity carried with its
+  // increment, as CellProblem::fdiff); the balancing constants cancel except inside the
+  // temperature row, which uses the forced derivatives.
+  void fdiff(const double* u, const double* du, double* out) const {
+    const int ns = m->n_species, nr = m->n_reactions;
+    const double T = u[ns], dT = du[ns], T1 = T + dT;
+    const double rho = u[ns + 1], drho = du[ns + 1];
+    std::vector<double> c(ns), dc(ns), wdot(ns, 0.0), dwdot(ns, 0.0);
+    for (int k = 0; k < ns; ++k) {
+      c[k] = 1e-6 * u[k] / m->W[k];
+      dc[k] = 1e-6 * du[k] / m->W[k];
+    }
+    const double lnT = std::log(T), dlnT = std::log1p(dT / T);
+    const double invRT = 1.0 / (kRu * T), dinvRT = -dT / (kRu * T * T1);
+    for (int j = 0; j < nr; ++j) {
+      const double kf = std::exp(m->lnAf[j] + m->bf[j] * lnT - m->Ef[j] * invRT);
+      const double kr = std::exp(m->lnAr[j] + m->br[j] * lnT - m->Er[j] * invRT);
+      const double dkf = kf * std::expm1(m->bf[j] * dlnT - m->Ef[j] * dinvRT);
+      const double dkr = kr * std::expm1(m->br[j] * dlnT - m->Er[j] * dinvRT);
+      double pf = 1.0, dpf = 0.0, pr = 1.0, dpr = 0.0;
+      for (int a = 0; a < 2; ++a) {
+        const int r = m->reac[2 * j + a];
+        if (r >= 0) { dpf = (pf + dpf) * dc[r] + dpf * c[r]; pf = pf * c[r]; }
+        const int q = m->prod[2 * j + a];
+        if (q >= 0) { dpr = (pr + dpr) * dc[q] + dpr * c[q]; pr = pr * c[q]; }
+      }
+      const double q = kf * pf - kr * pr;
+      const double dq = ((kf + dkf) * dpf + dkf * pf) - ((kr + dkr) * dpr + dkr * pr);
+      for (int a = 0; a < 2; ++a) {
+        const int r = m->reac[2 * j + a];
+        if (r >= 0) { wdot[r] -= q; dwdot[r] -= dq; }
+        const int p = m->prod[2 * j + a];
+        if (p >= 0) { wdot[p] += q; dwdot[p] += dq; }
+      }
+    }
+    double esum = 0.0, desum = 0.0, D = 0.0, dD = 0.0;
+    for (int k = 0; k < ns; ++k) {
+      const double F = m->W[k] * (1e6 * wdot[k]) + srow(k);
+      const double dF = m->W[k] * (1e6 * dwdot[k]);
+      out[k] = dF;
+      const double cv = m->cp[k] - kRu / m->W[k];
+      const double ek = m->hf[k] + m->cp[k] * (T - kTref) - kRu * T / m->W[k], dek = cv * dT;
+      esum += ek * F;
+      desum += (ek + dek) * dF + dek * F;
+      D += u[k] * cv;
+      dD += du[k] * cv;
+    }
+    for (int i = 1; i <= 5; ++i) out[ns + i] = 0.0;
+    // v = m / rho: dv = (dm rho - m drho) / (rho (rho + drho)); d(|v|^2/2) = dv . (v + dv/2)
+    double ke = 0.0, vF = 0.0, dke = 0.0, dvF = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double mv = u[ns + 2 + d], dmv = du[ns + 2 + d];
+      const double v = mv / rho, dv = (dmv * rho - mv * drho) / (rho * (rho + drho));
+      const double Fm = srow(ns + 2 + d);
+      ke += v * v;
+      vF += v * Fm;
+      dke += dv * (v + 0.5 * dv);
+      dvF += dv * Fm;
+    }
+    const double Frho = srow(ns + 1), FE = srow(ns + 5);
+    const double N = -esum + 0.5 * ke * Frho - vF + FE;
+    const double dN = -desum + dke * Frho - dvF;
+    // f_T = N / D: the increment is dN / (D + dD) - N dD / (D (D + dD))
+    out[ns] = dN / (D + dD) - N * dD / (D * (D + dD));
+  }
+};
+
+// Temperature of the conservative variables U = (rho Y_1..rho Y_ns, rho, rho u (3),
+// rho E) of one cell: rho e = rho E - |rho u|^2 / (2 rho) = sum_k rho Y_k e_k(T), which
+// is linear in T for constant c_p,k.  Returns NaN where rho c_v <= 0.
+double cons_temperature(const orc_mech* m, const double* U) {
+  const int ns = m->n_species;
+  const double rho = U[ns];
+  double e0 = 0.0, D = 0.0, m2 = 0.0;
+  for (int k = 0; k < ns; ++k) {
+    e0 += U[k] * (m->hf[k] - m->cp[k] * kTref);
+    D += U[k] * (m->cp[k] - kRu / m->W[k]);
+  }
+  for (int d = 0; d < 3; ++d) m2 += U[ns + 1 + d] * U[ns + 1 + d];
+  if (!(D > 0.0)) return std::numeric_limits<double>::quiet_NaN();
+  return (U[ns + 4] - 0.5 * m2 / rho - e0) / D;
+}
 
 // Linear test problem f(u) = A u + c (A row-major n x n).
 struct LinearProblem {
@@ -851,6 +1008,104 @@ int orc_integrate(const orc_mech* m, const orc_opts* o, int64_t n, double* Y, do
                   const double* p, const double* S, double dt, double rtol, double atol,
                   int32_t* acc, int32_t* rej, int32_t* status, int nthreads) {
   return orc_integrate_h(m, o, n, Y, T, p, S, dt, rtol, atol, nullptr, acc, rej, status, nthreads);
+}
+
+// ---------------------------------------------- conservative variables (Sec. 5) ----
+// U: [(ns+5) * n] structure of arrays, rows rho Y_1..rho Y_ns, rho, rho u_x, rho u_y,
+// rho u_z, rho E (SI units); S: the balancing constants, same layout, may be null.
+
+// Temperature of every cell's conservative variables (NaN where rho c_v <= 0).
+int orc_cons_temperature(const orc_mech* m, int64_t n, const double* U, double* T) {
+  const int ns = m->n_species;
+  std::vector<double> col(ns + 5);
+  for (int64_t c = 0; c < n; ++c) {
+    for (int r = 0; r < ns + 5; ++r) col[r] = U[r * n + c];
+    T[c] = cons_temperature(m, col.data());
+  }
+  return 0;
+}
+
+// f of one cell in the auxiliary-temperature state u (length ns+6); s may be null.
+int orc_cons_f(const orc_mech* m, const double* u, const double* s, double* out) {
+  ConsProblem prob{m, s};
+  prob.f<double>(u, out);
+  return 0;
+}
+
+// f(u + du) - f(u) of one cell: difference form, or (quad != 0) both evaluations in
+// quadruple precision, rounded to double after the subtraction.
+int orc_cons_fdiff(const orc_mech* m, const double* u, const double* s, const double* du, int quad_,
+                   double* out) {
+  ConsProblem prob{m, s};
+  const int n = prob.n();
+  if (!quad_) {
+    prob.fdiff(u, du, out);
+    return 0;
+  }
+  std::vector<quad> a(n), b(n), fa(n), fb(n);
+  for (int i = 0; i < n; ++i) {
+    a[i] = (quad)u[i];
+    b[i] = (quad)u[i] + (quad)du[i];
+  }
+  prob.f<quad>(a.data(), fa.data());
+  prob.f<quad>(b.data(), fb.data());
+  for (int i = 0; i < n; ++i) out[i] = (double)(fb[i] - fa[i]);
+  return 0;
+}
+
+// J(u) v of one auxiliary-temperature cell in the given JVP mode (0 FD, 1 complex step).
+int orc_cons_jvp(const orc_mech* m, const double* u, const double* s, const double* v, int mode,
+                 double* out) {
+  ConsProblem prob{m, s};
+  const int n = prob.n();
+  std::vector<double> uu(u, u + n), fu(n);
+  prob.f<double>(uu.data(), fu.data());
+  return jvp(prob, mode, std::ldexp(1.0, -52), uu, fu, v, out) ? 0 : -1;
+}
+
+// Integrates n cells of conservative variables over [0, dt] in place: the auxiliary
+// temperature starts from the temperature of U, the state (rho Y, T, rho, rho u, rho E)
+// is integrated by ROK4E, U receives the conservative rows at dt and T_aux (optional)
+// the auxiliary temperature at dt.  A cell with non-finite input, rho <= 0,
+// rho c_v <= 0 or T <= 0 keeps its state and reports status 3.
+int orc_integrate_cons(const orc_mech* m, const orc_opts* o, int64_t n, double* U, const double* S,
+                       double dt, double rtol, double atol, double* T_aux, int32_t* acc, int32_t* rej,
+                       int32_t* status, int nthreads) {
+  const int ns = m->n_species;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  for (int64_t c = 0; c < n; ++c) {
+    Result r;
+    std::vector<double> col(ns + 5), u(ns + 6), s;
+    bool ok = true;
+    for (int i = 0; i < ns + 5; ++i) {
+      col[i] = U[i * n + c];
+      ok = ok && std::isfinite(col[i]);
+    }
+    const double T0 = ok ? cons_temperature(m, col.data()) : 0.0;
+    ok = ok && col[ns] > 0.0 && std::isfinite(T0) && T0 > 0.0;
+    if (!ok) {
+      r.status = 3;
+    } else {
+      for (int k = 0; k < ns; ++k) u[k] = col[k];
+      u[ns] = T0;
+      for (int i = 0; i < 5; ++i) u[ns + 1 + i] = col[ns + i];
+      if (S) {
+        s.assign(ns + 6, 0.0);
+        for (int k = 0; k < ns; ++k) s[k] = S[k * n + c];
+        for (int i = 0; i < 5; ++i) s[ns + 1 + i] = S[(ns + i) * n + c];
+      }
+      ConsProblem prob{m, S ? s.data() : nullptr};
+      r = rok4e_one(prob, u, dt, rtol, atol, *o);
+      for (int k = 0; k < ns; ++k) U[k * n + c] = u[k];
+      for (int i = 0; i < 5; ++i) U[(ns + i) * n + c] = u[ns + 1 + i];
+      if (T_aux) T_aux[c] = u[ns];
+    }
+    if (acc) acc[c] = r.accepted;
+    if (rej) rej[c] = r.rejected;
+    if (status) status[c] = r.status;
+  }
+  return 0;
 }
 
 // ROK4E on the linear problem u' = A u + c (A row-major n x n), u in place.
