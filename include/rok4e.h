@@ -169,6 +169,31 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* mech, double* Y, double* T, 
                        const double* S, double* h_io, double dt, double rtol, double atol,
                        void* stream);
 
+/* Reaction substep in the conservative variables of a compressible flow solver with the
+ * auxiliary temperature equation (Sec. 5, e:chemical_source_balanced and
+ * e:aux_t_equation).  U[(ns+5) * n_cells] (device, FP64, structure of arrays with stride
+ * n_cells; read and overwritten) holds per cell rho Y_1 .. rho Y_ns (kg/m^3), rho,
+ * rho u_x, rho u_y, rho u_z (kg/(m^2 s)) and rho E (J/m^3, E the total energy per unit
+ * mass including the formation enthalpies: E = sum_k Y_k e_k(T) + |u|^2 / 2 with
+ * e_k = h_f,k + c_p,k (T - 298.15) - Ru T / W_k).  S (same layout, may be NULL) holds
+ * each row's balancing constant, the transport term of the conservative variables at the
+ * start of the step.  The temperature is computed from U at the start of each cell's
+ * integration and integrated with the state (ns + 6 rows: the species, T, rho, rho u,
+ * rho E) with the source
+ *   dT/dt = (-sum_k e_k F_k + |u|^2/2 F_rho - u . F_m + F_E) / (rho c_v),
+ * F the forced derivatives of the conservative rows and rho c_v = sum_k rho Y_k
+ * (c_p,k - Ru / W_k); the species energy of e:aux_t_equation is read as the internal
+ * energy, under which the auxiliary temperature equals the temperature of U along the
+ * exact solution.  The chemistry is that of a constant-volume reactor (c_k = rho Y_k /
+ * W_k).  T_aux[n_cells] (device, may be NULL) receives the auxiliary temperature at dt.
+ * A cell with non-finite input, rho <= 0, rho c_v <= 0 or a temperature <= 0 keeps U
+ * (and its T_aux entry) and reports status 3.  Persistent schedule, FP64, ROK4E only,
+ * and a layout of at least ns + 6 rows (lanes_per_cell x slots); ROK4E_ENOTSUP
+ * otherwise.  Cells are handed out in array order; per-cell statistics as for
+ * rok4e_integrate. */
+int rok4e_integrate_conservative(int64_t n_cells, rok4e_mech* mech, double* U, const double* S,
+                                 double* T_aux, double dt, double rtol, double atol, void* stream);
+
 /* Launch tuning: integrates a copy of the given batch (Y, T, p as for rok4e_integrate;
  * the caller's arrays are not modified) once per waves-per-block choice 1..4 with the
  * handle's other options, times each with HIP events after a warm-up run, and keeps the

@@ -78,7 +78,10 @@ __global__ void __launch_bounds__(256) k_order_scatter(const double* T, int64_t 
 template <int ROWS>
 constexpr int occupancy() { return ROWS == 1 ? ROK4E_OCC_ROWS1 : 2; }
 
-template <int L, int ROWS, int MMAX, class RT>
+// FORM selects the state: the 0-D reactor (Y, T; p per cell) or the conservative
+// variables with the auxiliary temperature (P.Y = U, P.T = the final temperatures or
+// null; FP64; array order, no carried steps).
+template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor>
 __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m, Launch P) {
   extern __shared__ __align__(16) char smem[];
   const MechLds t = load_mech_lds<L>(m, smem);
@@ -93,10 +96,15 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m,
     const int tk = seg_bcast<L>((int)ticket, 0);
     if (tk < 0 || (int64_t)tk >= P.n_cells) break;
     const int cell = P.order ? P.order[tk] : tk;
-    double u[ROWS], s[ROWS], p;
+    double u[ROWS], s[ROWS], p = 0.0;
     CellState c{};
     c.status = 3;
-    if (load_cell<L, ROWS>(m, P, cell, lane, u, s, p)) {
+    if constexpr (FORM == kFormConservative) {
+      if (load_cell_cons<L, ROWS>(m, t, P, cell, lane, u, s)) {
+        c = integrate_cell<L, ROWS, MMAX, RT, FORM>(m, t, P, u, p, s, S, lane);
+        store_cell_cons<L, ROWS>(m, P, cell, lane, u);
+      }
+    } else if (load_cell<L, ROWS>(m, P, cell, lane, u, s, p)) {
       c = integrate_cell<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane, P.hio ? P.hio[cell] : 0.0);
       store_cell<L, ROWS>(m, P, cell, lane, u);
       if (P.hio) P.hio[cell] = c.hnext;
@@ -297,14 +305,22 @@ using ArnoldiFn = void (*)(DevMech, Launch, double*, double*, int32_t*);
 struct Variant {
   int L, rows, mmax, prec;
   IntegrateFn integrate;
+  IntegrateFn integrate_cons;   // conservative variables (FP64 variants; null otherwise)
   IntegrateFn rkdp;
   AttemptFn attempt;
   ArnoldiFn arnoldi;
   RhsFn rhs;
 };
 
+template <int L, int ROWS, int MMAX, class RT>
+constexpr IntegrateFn cons_kernel() {
+  if constexpr (sizeof(RT) == 8) return k_integrate<L, ROWS, MMAX, RT, kFormConservative>;
+  else return nullptr;
+}
+
 #define ROK4E_VARIANT(Lv, Rv, Mv, T, P)                                                       \
-  Variant{Lv, Rv, Mv, P, k_integrate<Lv, Rv, Mv, T>, k_rkdp<Lv, Rv, T>, k_attempt<Lv, Rv, Mv, T>,         \
+  Variant{Lv, Rv, Mv, P, k_integrate<Lv, Rv, Mv, T>, cons_kernel<Lv, Rv, Mv, T>(),             \
+          k_rkdp<Lv, Rv, T>, k_attempt<Lv, Rv, Mv, T>,                                         \
           k_arnoldi<Lv, Rv, Mv, T>,                                                             \
           k_rhs<Lv, Rv, T>}
 
@@ -843,6 +859,36 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
   launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
   hipLaunchKernelGGL(m->var->integrate, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e);
+  m->last_n = n_cells;
+  return ROK4E_OK;
+}
+
+int rok4e_integrate_conservative(int64_t n_cells, rok4e_mech* m, double* U, const double* S,
+                                 double* T_aux, double dt, double rtol, double atol, void* stream) {
+  if (!m || n_cells < 0 || n_cells > INT32_MAX - 1 || (n_cells > 0 && !U)) return ROK4E_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(rtol > 0.0) || !(atol >= 0.0) || !std::isfinite(rtol) ||
+      !std::isfinite(atol))
+    return ROK4E_EINVAL;
+  if (m->opt.precision != ROK4E_FP64 || m->opt.method != ROK4E_METHOD_ROK4E ||
+      m->opt.scheduling != ROK4E_PERSISTENT || !m->var->integrate_cons ||
+      m->var->L * m->var->rows < m->ns + 6)
+    return ROK4E_ENOTSUP;
+  if (n_cells == 0) return ROK4E_OK;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ensure_workspace(m, n_cells, st);
+  if (rc) return rc;
+  const SegLayout sl = seg_layout(m->nr, *m->var);
+  Launch P = base_launch(m, n_cells, U, T_aux, nullptr, S, sl);
+  P.dt = dt;
+  P.rtol = rtol;
+  P.atol = atol;
+  LaunchShape sh;
+  rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate_cons, true, &sh);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
+  hipLaunchKernelGGL(m->var->integrate_cons, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e);
   m->last_n = n_cells;

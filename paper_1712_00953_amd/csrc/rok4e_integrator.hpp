@@ -1,6 +1,7 @@
 // Per-cell ROK4E integration on one segment of lanes (Algorithm a:ROK4E).
 #pragma once
 
+#include "rok4e_cons.hpp"
 #include "rok4e_device.hpp"
 
 namespace rok4e {
@@ -34,15 +35,32 @@ __device__ __forceinline__ void init_seg(const DevMech& m, const SegLds<RT>& S) 
   lds_sync();
 }
 
+// State forms: the 0-D reactor (Y_k, T) at constant pressure, or the conservative
+// variables of a compressible solver with the auxiliary temperature (ns + 6 rows).
+constexpr int kFormReactor = 0, kFormConservative = 1;
+
+template <int FORM> struct BaseOf { using type = RhsBase; };
+template <> struct BaseOf<kFormConservative> { using type = RhsBaseCons; };
+
+template <int FORM>
+__device__ __forceinline__ int state_rows(const DevMech& m) {
+  return FORM == kFormConservative ? m.ns + 6 : m.ns + 1;
+}
+
 // f(u) + s for the rows this lane holds (SAVE keeps the base quantities for rhs_diff).
-template <int L, int ROWS, class RT, bool SAVE>
+template <int L, int ROWS, class RT, bool SAVE, int FORM = kFormReactor>
 __device__ __forceinline__ void rhs_forced(const DevMech& m, const MechLds& t, const double (&u)[ROWS],
                                            double p, const double (&s)[ROWS], double (&f)[ROWS],
-                                           const SegLds<RT>& S, int lane, RhsBase* base,
-                                           RT (&w)[ROWS]) {
-  rhs<L, ROWS, RT, SAVE>(m, t, u, p, f, S.r, lane, base, w);
+                                           const SegLds<RT>& S, int lane,
+                                           typename BaseOf<FORM>::type* base, RT (&w)[ROWS]) {
+  if constexpr (FORM == kFormConservative) {
+    static_assert(sizeof(RT) == 8, "the conservative form is FP64 only");
+    rhs_cons<L, ROWS, SAVE>(m, t, u, s, f, S.r, lane, base, w);
+  } else {
+    rhs<L, ROWS, RT, SAVE>(m, t, u, p, f, S.r, lane, base, w);
 #pragma unroll
-  for (int i = 0; i < ROWS; ++i) f[i] = f[i] + s[i];
+    for (int i = 0; i < ROWS; ++i) f[i] = f[i] + s[i];
+  }
 }
 
 // Arnoldi process with modified Gram-Schmidt and one classical re-orthogonalisation pass
@@ -51,12 +69,13 @@ __device__ __forceinline__ void rhs_forced(const DevMech& m, const MechLds& t, c
 // numerator in difference form.  Q holds this lane's rows of the orthonormal basis, H
 // (LDS) the M x M Hessenberg matrix; both FP64.  Returns M_eff.  Needs the base
 // evaluation of f at u (rhs with SAVE) just before.
-template <int L, int ROWS, int MMAX, class RT>
+template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor>
 __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const Launch& P,
                                        const double (&u)[ROWS],
-                                       const double (&fn)[ROWS], const RhsBase& B, const RT (&w)[ROWS],
-                                       double (&Q)[ROWS][MMAX], const SegLds<RT>& S, int lane) {
-  const int N = m.ns + 1;
+                                       const double (&fn)[ROWS], const typename BaseOf<FORM>::type& B,
+                                       const RT (&w)[ROWS], double (&Q)[ROWS][MMAX],
+                                       const SegLds<RT>& S, int lane) {
+  const int N = state_rows<FORM>(m);
   int Meff = P.M < N ? P.M : N;
 #pragma unroll
   for (int i = 0; i < ROWS; ++i)
@@ -102,7 +121,10 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
     double du[ROWS], d[ROWS], wv[ROWS];
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) du[i] = delta * Q[i][j];
-    rhs_diff<L, ROWS, RT, NIT>(m, t, B, w, u, du, d, S.r, lane, cached ? &cache : nullptr);
+    if constexpr (FORM == kFormConservative)
+      rhs_diff_cons<L, ROWS, NIT>(m, t, B, w, u, du, d, S.r, lane, cached ? &cache : nullptr);
+    else
+      rhs_diff<L, ROWS, RT, NIT>(m, t, B, w, u, du, d, S.r, lane, cached ? &cache : nullptr);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) wv[i] = d[i] * rdelta;
     double hj[MMAX];
@@ -318,12 +340,12 @@ __device__ __forceinline__ bool cell_running(const Launch& P, CellState& c) {
 // readings: clipped last step, err_n = 1 before the first acceptance and updated on
 // acceptance, basis (fn, Q, the LDS copy of H, M_eff) reused after a rejection,
 // non-finite u* or err rejected.
-template <int L, int ROWS, int MMAX, class RT>
+template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor>
 __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& tab, const Launch& P,
                                              double (&u)[ROWS], double p, const double (&s)[ROWS],
                                              const SegLds<RT>& S, int lane, CellState& c,
                                              double (&fn)[ROWS], double (&Q)[ROWS][MMAX]) {
-  const int N = m.ns + 1;
+  const int N = state_rows<FORM>(m);
   const double dt = P.dt;
   const double tiny = 16.0 * 2.220446049250313e-16 * dt;
   const bool fixed = P.fixed_steps > 0;
@@ -336,9 +358,9 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
   const double hprop = c.h;
   if (!c.basis_valid) {
     RT wbase[ROWS];
-    RhsBase base;
-    rhs_forced<L, ROWS, RT, true>(m, tab, u, p, s, fn, S, lane, &base, wbase);
-    c.Meff = arnoldi<L, ROWS, MMAX, RT>(m, tab, P, u, fn, base, wbase, Q, S, lane);
+    typename BaseOf<FORM>::type base;
+    rhs_forced<L, ROWS, RT, true, FORM>(m, tab, u, p, s, fn, S, lane, &base, wbase);
+    c.Meff = arnoldi<L, ROWS, MMAX, RT, FORM>(m, tab, P, u, fn, base, wbase, Q, S, lane);
     c.basis_valid = 1;
   }
   unsigned piv;
@@ -360,7 +382,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
   // Stage 2: F2 = f(u + h a21 k1) + (g21/g) k1.
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A21 * k1[i]);
-  rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
+  rhs_forced<L, ROWS, RT, false, FORM>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     corr[i] = (G21 / G) * k1[i];
@@ -370,7 +392,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
   // Stage 3: F3 = f(u + h(a31 k1 + a32 k2)) + (g31 k1 + g32 k2)/g.
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) arg[i] = u[i] + h * (A31 * k1[i] + A32 * k2[i]);
-  rhs_forced<L, ROWS, RT, false>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
+  rhs_forced<L, ROWS, RT, false, FORM>(m, tab, arg, p, s, fs, S, lane, nullptr, wtmp);
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     corr[i] = (G31 * k1[i] + G32 * k2[i]) * (1.0 / G);
@@ -438,7 +460,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
 }
 
 // Integrates the segment's cell over [0, dt] in place in u (all attempts).
-template <int L, int ROWS, int MMAX, class RT>
+template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor>
 __device__ __forceinline__ CellState integrate_cell(const DevMech& m, const MechLds& tab,
                                                     const Launch& P, double (&u)[ROWS], double p,
                                                     const double (&s)[ROWS], const SegLds<RT>& S,
@@ -446,7 +468,7 @@ __device__ __forceinline__ CellState integrate_cell(const DevMech& m, const Mech
   CellState c;
   cell_start(P, c, h0c);
   double fn[ROWS], Q[ROWS][MMAX];
-  while (cell_running(P, c)) cell_attempt<L, ROWS, MMAX, RT>(m, tab, P, u, p, s, S, lane, c, fn, Q);
+  while (cell_running(P, c)) cell_attempt<L, ROWS, MMAX, RT, FORM>(m, tab, P, u, p, s, S, lane, c, fn, Q);
   return c;
 }
 

@@ -27,7 +27,7 @@ CELL_OK, CELL_MAX_ATTEMPTS, CELL_STEP_UNDERFLOW, CELL_BAD_INPUT = 0, 1, 2, 3
 
 EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "rok4e_set_options",
            "rok4e_get_options", "rok4e_reserve", "rok4e_integrate", "rok4e_integrate_forced",
-           "rok4e_integrate_ex",
+           "rok4e_integrate_ex", "rok4e_integrate_conservative",
            "rok4e_tune", "rok4e_rhs", "rok4e_arnoldi", "rok4e_transport", "rok4e_split_workspace_bytes",
            "rok4e_split_step", "rok4e_get_stats", "rok4e_cell_stats_ptr",
            "rok4e_copy_cell_stats", "rok4e_strerror"]
@@ -89,6 +89,7 @@ def load():
         lib.rok4e_integrate.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_forced.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_ex.argtypes = [i64, vp, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
+        lib.rok4e_integrate_conservative.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_tune.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_float), vp]
         lib.rok4e_rhs.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
@@ -223,6 +224,20 @@ class Mech:
         rc = load().rok4e_integrate_ex(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(S), _ptr(h), float(dt),
                                        float(rtol), float(atol), _stream(stream))
         _check(rc, "rok4e_integrate")
+        self.n_last = n
+
+    def integrate_conservative(self, U, dt, rtol, atol, S=None, T_aux=None, stream=None, n_cells=None):
+        """In-place reaction substep of the conservative variables U [(ns+5), n] (float64
+        device tensor: rho Y_k, rho, rho u (3), rho E) with the auxiliary temperature;
+        S: balancing constants of the same shape, T_aux [n]: the final auxiliary
+        temperatures (rok4e_integrate_conservative)."""
+        n = int(U.shape[-1]) if n_cells is None else int(n_cells)
+        ns = self.n_species
+        for t, cnt, name in ((U, (ns + 5) * n, "U"), (S, (ns + 5) * n, "S"), (T_aux, n, "T_aux")):
+            _need(t, cnt, name)
+        rc = load().rok4e_integrate_conservative(n, self._h, _ptr(U), _ptr(S), _ptr(T_aux), float(dt),
+                                                 float(rtol), float(atol), _stream(stream))
+        _check(rc, "rok4e_integrate_conservative")
         self.n_last = n
 
     def tune(self, Y, T, p, dt, rtol, atol, stream=None) -> tuple[int, float]:
