@@ -10,7 +10,8 @@ Prints one JSON line: FP64 cell-integrations/s as `value`, the mixed-precision f
 and speed-up beside it, the roofline of the integration kernel (algorithmic FP64
 operations / kernel time against the FP64 vector peak), the standalone right-hand-side
 and Arnoldi kernels against the same peak, persistent vs per-attempt scheduling on the
-262,144-cell bimodal batch, one Simpler balanced splitting step on a 128^3 grid at CFL 0.5, and the
+262,144-cell bimodal batch, one Simpler balanced splitting step on a 128^3 grid at CFL 0.5, the
+substep in conservative variables with the auxiliary temperature on the same batch, and the
 CPU oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
@@ -202,6 +203,49 @@ def run_schedules(R, torch, synth):
     return out
 
 
+def run_conservative(w, R, torch, reps=3, v_scale=50.0, a=1e3, seed=5):
+    """The reaction substep in conservative variables with the auxiliary temperature
+    (rok4e_integrate_conservative) on the same 65,536-cell batch: the states moved to
+    (rho Y_k, rho, rho u, rho E) with seeded velocities (50 m/s per component) and a
+    seeded balancing constant on every row (1e3 /s times the row's magnitude)."""
+    st = w.states
+    n = st.n_cells
+    rng = np.random.default_rng(seed)
+    vel = v_scale * rng.standard_normal((3, n))
+    Ru = 8.314462618
+    Wk = np.asarray(w.mech.W)[:, None]
+    cp = np.asarray(w.mech.cp)[:, None]
+    hf = np.asarray(w.mech.hf)[:, None]
+    rho = st.p / (Ru * st.T * (st.Y / Wk).sum(0))
+    e = (st.Y * (hf + cp * (st.T - 298.15) - Ru * st.T / Wk)).sum(0)
+    U = np.vstack([rho * st.Y, rho[None], rho * vel, (rho * (e + 0.5 * (vel * vel).sum(0)))[None]])
+    S = a * np.abs(U) * rng.standard_normal(U.shape)
+    dev = torch.device("cuda:0")
+    U0 = torch.tensor(U, dtype=torch.float64, device=dev)
+    Sd = torch.tensor(S, dtype=torch.float64, device=dev)
+    Ta = torch.empty(n, dtype=torch.float64, device=dev)
+    m = R.Mech(w.mech, M=w.M, max_attempts=200000)
+    m.reserve(n)
+    Ud = U0.clone()
+    m.integrate_conservative(Ud, w.dt, w.rtol, w.atol, S=Sd, T_aux=Ta)
+    times = []
+    for _ in range(reps):
+        Ud.copy_(U0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.integrate_conservative(Ud, w.dt, w.rtol, w.atol, S=Sd, T_aux=Ta)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    s = m.stats()
+    m.close()
+    el = float(np.median(times))
+    return {"cells_per_s": n / el, "ms": el * 1e3, "attempts": s["accepted"] + s["rejected"],
+            "max_attempts_cell": s["max_attempts"], "status_count": s["status_count"],
+            "state_rows": int(w.mech.n_species) + 6,
+            "inputs": "flame-slice states in conservative variables, velocities N(0, 50 m/s), "
+                      "balancing constants 1e3/s x |U| x N(0, 1)"}
+
+
 def run_splitting(R, torch, synth, nx=128, h=5e-6, reps=2):
     """One Simpler balanced splitting step on an nx^3 periodic grid carrying the 53-species
     flame profile along x (advection 10 m/s, diffusivity 2e-5 m^2/s, dx = 1e-4 m, so
@@ -387,11 +431,13 @@ def main():
     if not args.no_mixed:
         mixed = run_gpu(w, R.MIXED, args.steps, args.warmup, R, torch)
         log(f"mixed: {mixed['cells_per_s']:.4e} cells/s, {mixed['ms_per_step']:.2f} ms/step")
-    subsystems = schedules = splitting = None
+    subsystems = schedules = splitting = conservative = None
     if not args.no_extras:
         subsystems = run_subsystems(w, R, torch)
         log("subsystems: " + ", ".join(f"{k} {v['kernel_ms']:.3f} ms ({v['frac'] * 100:.1f}% of FP64 peak)"
                                        for k, v in subsystems.items()))
+        conservative = run_conservative(w, R, torch)
+        log(f"conservative variables: {conservative['ms']:.1f} ms, {conservative['attempts']} attempts")
         schedules = run_schedules(R, torch, synth)
         log(f"schedules: persistent {schedules['persistent']['ms']:.1f} ms, per-attempt "
             f"{schedules['per_attempt']['ms']:.1f} ms, bitwise equal {schedules['bitwise_equal']}")
@@ -483,6 +529,8 @@ def main():
         out["schedules"] = schedules
     if splitting is not None:
         out["splitting"] = splitting
+    if conservative is not None:
+        out["conservative"] = conservative
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -34,6 +34,7 @@ def R():
 def cons_case(orc, cfg, n, seed=5, a=1e3, v_scale=50.0):
     w = synth.workload(cfg, a_scale=1e-8, n_cells=n)
     st = w.states
+    n = st.n_cells
     rng = np.random.default_rng(seed)
     vel = v_scale * rng.standard_normal((3, n))
     U = orc.cons_state(w.mech, st.Y, st.T, st.p, vel)
@@ -143,3 +144,26 @@ def test_conservative_edge_cases(R, orc):
     with pytest.raises(ValueError):
         m.integrate_conservative(Ud[:ns], w.dt, w.rtol, w.atol, n_cells=6)
     m.close()
+
+
+def test_conservative_full_batch_sampled(R, orc):
+    # the 65,536-cell flame slice in conservative variables, in the benchmark's launch
+    # configuration; a temperature-stratified sample of 48 cells against the oracle
+    w, U, S = cons_case(orc, 2, None)
+    ns = w.mech.n_species
+    g = gpu_cons(R, w, U, S, w.rtol, w.atol)
+    assert np.all(g[4] == 0)
+    idx = synth.stratified_sample(w.states.T, 48, 404)
+    o = orc.integrate_cons(w.mech, U[:, idx], w.dt, w.rtol, w.atol, w.M, S=S[:, idx])
+    tw = orc.integrate_cons(w.mech, U[:, idx], w.dt, w.rtol, w.atol, w.M, S=S[:, idx], fma=True)
+    gs = tuple(x[..., idx] for x in g)
+    env = rel_max(tw, o, ns)
+    got = rel_max(gs, o, ns)
+    match = (gs[2] == o[2]) & (gs[3] == o[3])
+    twin_match = (tw[2] == o[2]) & (tw[3] == o[3])
+    print(f"\n[cons full cfg2] n={U.shape[1]} sample=48 rel={got:.3e} twin={env:.3e} "
+          f"match={match.mean():.3f}", flush=True)
+    assert got <= max(1e-10, 4 * env)
+    assert match[twin_match].mean() >= 0.98
+    Tc = orc.cons_temperature(w.mech, g[0])
+    assert float((np.abs(g[1] - Tc) / Tc).max()) <= 10 * w.rtol
