@@ -13,9 +13,11 @@
 // temperature equals the temperature of the conservative variables along the exact
 // solution, which the paper states of the method.
 //
-// FP64 only.  The reaction loops are those of rhs / rhs_diff with the constant-volume
-// concentrations; the tables, the LDS scratch layout and the base-concentration cache of
-// the Arnoldi process are shared with them.
+// FP64 only; the reciprocals of the cell-uniform quantities (T, rho, rho c_v and their
+// perturbed values, all positive) use the refined hardware reciprocal.  The reaction
+// loops are those of rhs / rhs_diff with the constant-volume concentrations; the tables,
+// the LDS scratch layout and the base-concentration cache of the Arnoldi process are
+// shared with them.
 #pragma once
 
 #include "rok4e_device.hpp"
@@ -62,7 +64,7 @@ __device__ __forceinline__ void rhs_cons(const DevMech& m, const MechLds& t, con
     }
   }
   const double lnT = log(T);
-  const double invT = 1.0 / T;
+  const double invT = rcp(T);
   const double invRT = invT * (1.0 / kRu);
   char* rb = (char*)S.spc;
   lds_sync();
@@ -97,12 +99,12 @@ __device__ __forceinline__ void rhs_cons(const DevMech& m, const MechLds& t, con
   }
   seg_sum_rows_k<L, ROWS, 2>(es, sums);
   const double D = sums[1];
-  const double irho = 1.0 / rho;
+  const double irho = rcp(rho);
   const double vx = mx * irho, vy = my * irho, vz = mz * irho;
   const double ke = vx * vx + vy * vy + vz * vz;
   const double vF = vx * Fmx + vy * Fmy + vz * Fmz;
   const double N = -sums[0] + 0.5 * ke * Frho - vF + FE;
-  const double fT = N / D;
+  const double fT = N * rcp(D);
 #pragma unroll
   for (int i = 0; i < ROWS; ++i)
     if (i * L + lane == ns) f[i] = fT;
@@ -139,7 +141,7 @@ __device__ __forceinline__ void rhs_diff_cons(const DevMech& m, const MechLds& t
     }
   }
   const double dlnT = log1p_small(dT * B.invT);
-  const double dinvRT = -dT * (B.invRT / T1);
+  const double dinvRT = -dT * (B.invRT * rcp(T1));
   char* rb = (char*)S.spc;
   lds_sync();
   auto diff_rx = [&](int j, const uint2 o, double ca, double cb, double cc_, double cd) {
@@ -196,14 +198,14 @@ __device__ __forceinline__ void rhs_diff_cons(const DevMech& m, const MechLds& t
   seg_sum_rows_k<L, ROWS, 2>(es, sums);
   const double dD = sums[1];
   // v = m / rho: dv = (dm - v drho) / (rho + drho); d(|v|^2 / 2) = dv . (v + dv / 2)
-  const double irho1 = 1.0 / (B.rho + drho);
+  const double irho1 = rcp(B.rho + drho);
   const double dvx = (dmx - B.vx * drho) * irho1, dvy = (dmy - B.vy * drho) * irho1,
                dvz = (dmz - B.vz * drho) * irho1;
   const double dke = dvx * (B.vx + 0.5 * dvx) + dvy * (B.vy + 0.5 * dvy) + dvz * (B.vz + 0.5 * dvz);
   const double dvF = dvx * B.Fmx + dvy * B.Fmy + dvz * B.Fmz;
   const double dN = -sums[0] + dke * B.Frho - dvF;
-  const double D1 = B.D + dD;
-  const double dfT = dN / D1 - B.N * dD / (B.D * D1);
+  const double iD1 = rcp(B.D + dD);
+  const double dfT = (dN - B.N * dD * rcp(B.D)) * iD1;
 #pragma unroll
   for (int i = 0; i < ROWS; ++i)
     if (i * L + lane == ns) df[i] = dfT;
