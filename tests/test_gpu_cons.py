@@ -167,3 +167,41 @@ def test_conservative_full_batch_sampled(R, orc):
     assert match[twin_match].mean() >= 0.98
     Tc = orc.cons_temperature(w.mech, g[0])
     assert float((np.abs(g[1] - Tc) / Tc).max()) <= 10 * w.rtol
+
+
+@pytest.mark.parametrize("lanes", [16, 32])
+def test_conservative_small_layouts(R, orc, lanes):
+    # the 9-species workload on 16 lanes (15 state rows) and the 53-species workload on
+    # 32 lanes x 2 slots; on the 9-species states the mixture c_v is negative for about a
+    # third of the cells, which both sides must refuse with status 3
+    import torch
+    cfg, n = (1, 256) if lanes == 16 else (2, 128)
+    w, U, S = cons_case(orc, cfg, n)
+    ns = w.mech.n_species
+    o = orc.integrate_cons(w.mech, U, w.dt, w.rtol, w.atol, w.M, S=S)
+    tw = orc.integrate_cons(w.mech, U, w.dt, w.rtol, w.atol, w.M, S=S, fma=True)
+    m = R.Mech(w.mech, M=w.M, lanes_per_cell=lanes)
+    Ud = torch.tensor(U, dtype=torch.float64, device="cuda:0")
+    Sd = torch.tensor(S, dtype=torch.float64, device="cuda:0")
+    Ta = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0")
+    m.integrate_conservative(Ud, w.dt, w.rtol, w.atol, S=Sd, T_aux=Ta)
+    acc = torch.zeros(n, dtype=torch.int32)
+    rej = torch.zeros(n, dtype=torch.int32)
+    sta = torch.zeros(n, dtype=torch.int32)
+    m.cell_stats(acc, rej, sta)
+    torch.cuda.synchronize()
+    m.close()
+    g = (Ud.cpu().numpy(), Ta.cpu().numpy(), acc.numpy(), rej.numpy(), sta.numpy())
+    np.testing.assert_array_equal(g[4], o[4])
+    ok = o[4] == 0
+    bad = ~ok
+    print(f"\n[cons L={lanes} cfg{cfg}] refused {int(bad.sum())} of {n} cells", flush=True)
+    if cfg == 1:
+        assert bad.sum() > 0 and ok.sum() > 0
+    np.testing.assert_array_equal(g[0][:, bad], U[:, bad])
+    sub = lambda r: (r[0][:, ok], r[1][ok], r[2][ok], r[3][ok])
+    env = rel_max(sub(tw), sub(o), ns)
+    got = rel_max(sub(g), sub(o), ns)
+    print(f"[cons L={lanes} cfg{cfg}] rel={got:.3e} twin={env:.3e}", flush=True)
+    assert got <= max(1e-10, 4 * env)
+    assert np.mean((g[2] == o[2])[ok] & (g[3] == o[3])[ok]) >= 0.98
