@@ -9,10 +9,11 @@ mechanism; the literal draw is too stiff to integrate, see the design notes).
 Prints one JSON line: FP64 cell-integrations/s as `value`, the mixed-precision figure
 and speed-up beside it, the roofline of the integration kernel (algorithmic FP64
 operations / kernel time against the FP64 vector peak), the standalone right-hand-side
-and Arnoldi kernels against the same peak, persistent vs per-attempt scheduling on the
-262,144-cell bimodal batch, one Simpler balanced splitting step on a 128^3 grid at CFL 0.5, the
-substep in conservative variables with the auxiliary temperature on the same batch, and the
-CPU oracle timed on a bounded sample on this host.
+and Arnoldi kernels against the same peak, the substep in conservative variables with
+the auxiliary temperature on the flame slice, persistent vs per-attempt scheduling on the
+262,144-cell bimodal batch and the throughput of its prefixes from 4,096 cells up, one
+Simpler balanced splitting step on a 128^3 grid at CFL 0.5, and the CPU oracle timed on a
+bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -246,6 +247,40 @@ def run_conservative(w, R, torch, reps=3, v_scale=50.0, a=1e3, seed=5):
                       "balancing constants 1e3/s x |U| x N(0, 1)"}
 
 
+def run_curve(R, torch, synth, sizes=(4096, 16384, 32768, 65536, 131072, 262144), reps=2):
+    """Throughput against batch size on the 262,144-cell bimodal batch (its cells are
+    shuffled, so a prefix is a random subset): how far one GPU's share of a batch split
+    over several GPUs (32,768 cells at eight) stays from the full-batch rate."""
+    w = synth.workload(3, a_scale=A_SCALE)
+    st = w.states
+    dev = torch.device("cuda:0")
+    Y0 = torch.tensor(st.Y, dtype=torch.float64, device=dev)
+    T0 = torch.tensor(st.T, dtype=torch.float64, device=dev)
+    p0 = torch.tensor(st.p, dtype=torch.float64, device=dev)
+    m = R.Mech(w.mech, M=w.M, max_attempts=200000)
+    m.reserve(st.n_cells)
+    out = []
+    for n in sizes:
+        Yn, Tn, pn = Y0[:, :n].contiguous(), T0[:n].contiguous(), p0[:n].contiguous()
+        Y, T = Yn.clone(), Tn.clone()
+        m.integrate(Y, T, pn, w.dt, w.rtol, w.atol)
+        times = []
+        for _ in range(reps):
+            Y.copy_(Yn)
+            T.copy_(Tn)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.integrate(Y, T, pn, w.dt, w.rtol, w.atol)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        s = m.stats()
+        el = min(times)
+        out.append({"n_cells": n, "ms": el * 1e3, "cells_per_s": n / el,
+                    "attempts": s["accepted"] + s["rejected"], "max_attempts_cell": s["max_attempts"]})
+    m.close()
+    return {"workload": w.name + " (prefixes)", "points": out}
+
+
 def run_splitting(R, torch, synth, nx=128, h=5e-6, reps=2):
     """One Simpler balanced splitting step on an nx^3 periodic grid carrying the 53-species
     flame profile along x (advection 10 m/s, diffusivity 2e-5 m^2/s, dx = 1e-4 m, so
@@ -431,7 +466,7 @@ def main():
     if not args.no_mixed:
         mixed = run_gpu(w, R.MIXED, args.steps, args.warmup, R, torch)
         log(f"mixed: {mixed['cells_per_s']:.4e} cells/s, {mixed['ms_per_step']:.2f} ms/step")
-    subsystems = schedules = splitting = conservative = None
+    subsystems = schedules = splitting = conservative = curve = None
     if not args.no_extras:
         subsystems = run_subsystems(w, R, torch)
         log("subsystems: " + ", ".join(f"{k} {v['kernel_ms']:.3f} ms ({v['frac'] * 100:.1f}% of FP64 peak)"
@@ -439,6 +474,9 @@ def main():
         conservative = run_conservative(w, R, torch)
         log(f"conservative variables: {conservative['ms']:.1f} ms, {conservative['attempts']} attempts")
         schedules = run_schedules(R, torch, synth)
+        curve = run_curve(R, torch, synth)
+        log("batch-size curve: " + ", ".join(f"{q['n_cells']} cells {q['cells_per_s']:.3e}/s"
+                                            for q in curve["points"]))
         log(f"schedules: persistent {schedules['persistent']['ms']:.1f} ms, per-attempt "
             f"{schedules['per_attempt']['ms']:.1f} ms, bitwise equal {schedules['bitwise_equal']}")
         splitting = run_splitting(R, torch, synth)
@@ -531,6 +569,8 @@ def main():
         out["splitting"] = splitting
     if conservative is not None:
         out["conservative"] = conservative
+    if curve is not None:
+        out["batch_size_curve"] = curve
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
