@@ -417,9 +417,10 @@ const Variant* pick_variant(int ns, const rok4e_options& o) {
   return best;
 }
 
-// Per-segment LDS: concentrations and increments [2][LP] and the rate-constant pairs
-// [NRP] in the rate type, production accumulators [LP], H, LU [MMAX^2] and 1/diag(U)
-// [MMAX] in FP64.
+// Per-segment LDS: concentrations and increments [2][LP] in the rate type, the production
+// accumulators [LP] in FP64 (two copies LP + 8 entries apart in the mixed form), the
+// rate-constant pairs [NRP] in the rate type, H, LU [MMAX^2] and 1/diag(U) [MMAX] in
+// FP64.
 struct SegLayout {
   int bytes, off_k, off_H, off_LU, off_rdiag;
 };
@@ -434,7 +435,8 @@ SegLayout seg_layout(int nr, const Variant& v) {
   const int rt = rate_bytes(v.prec);
   const int lp = v.L * v.rows;
   SegLayout s{};
-  int off = al16(2 * lp * rt + lp * 8);
+  // concentrations and increments, accumulators (two copies in the mixed form)
+  int off = al16(2 * lp * rt + (rt == 4 ? 2 * lp + 8 : lp) * 8);
   s.off_k = off;
   off = al16(off + n_rx_padded(nr) * 2 * rt);
   s.off_H = off;
@@ -465,7 +467,7 @@ int ensure_image(rok4e_mech* m) {
     const int sl[4] = {m->reac[2 * j], m->reac[2 * j + 1], m->prod[2 * j], m->prod[2 * j + 1]};
     for (int a = 0; a < 4; ++a) slots[4 * j + a] = sl[a] < 0 ? ns : sl[a];
   }
-  PlacementSearch search(ns, nr, slots, m->var->L, rb);
+  PlacementSearch search(ns, nr, slots, m->var->L, rb, rb == 4 ? 2 * lp + 16 : 0);
   const Placement pl = search.run(kPlacementSteps, 0x5eed0000ull + (uint64_t)key);
   const int off_spec = al16(3 * nrp * 16);
   const int off_rxo = al16(off_spec + 4 * lp * 8);

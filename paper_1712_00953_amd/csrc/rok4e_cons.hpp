@@ -60,13 +60,14 @@ __device__ __forceinline__ void rhs_cons(const DevMech& m, const MechLds& t, con
     if (r < ns) {
       const int q = (ROWS == 1 ? t.rspos : t.spos[r]);
       S.spc[q] = 1e-6 * u[i] * (ROWS == 1 ? t.rinvW : t.invW[r]);
-      *acc_at<LP, double>((char*)S.spc, q * sizeof(double)) = 0.0;
+      acc_clear<LP, double>((char*)S.spc, q * sizeof(double));
     }
   }
   const double lnT = log(T);
   const double invT = rcp(T);
   const double invRT = invT * (1.0 / kRu);
   char* rb = (char*)S.spc;
+  char* ab = acc_base<LP, double>(rb, lane);
   lds_sync();
   for (int j = lane; j < m.nr; j += L) {
     const double2 lnA = t.lnA[j], bEf = t.bEf[j], bEr = t.bEr[j];
@@ -76,7 +77,7 @@ __device__ __forceinline__ void rhs_cons(const DevMech& m, const MechLds& t, con
     const uint2 o = t.rxo[j];
     const double pf = *(const double*)(rb + (o.x & 0xFFFFu)) * *(const double*)(rb + (o.x >> 16));
     const double pr = *(const double*)(rb + (o.y & 0xFFFFu)) * *(const double*)(rb + (o.y >> 16));
-    scatter_rate<LP, double>(rb, o, kf * pf - kr * pr);
+    scatter_rate<LP, double>(ab, o, kf * pf - kr * pr);
   }
   lds_sync();
   double es[ROWS][2], sums[2];
@@ -89,7 +90,7 @@ __device__ __forceinline__ void rhs_cons(const DevMech& m, const MechLds& t, con
     if (r < ns) {
       const double Wr = ROWS == 1 ? t.rW : t.W[r], iW = ROWS == 1 ? t.rinvW : t.invW[r];
       const double cp = ROWS == 1 ? t.rcp : t.cp[r], hf = ROWS == 1 ? t.rhf : t.hf[r];
-      const double F = Wr * (1e6 * *acc_at<LP, double>(rb, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(double))) + s[i];
+      const double F = Wr * (1e6 * acc_sum<LP, double>(rb, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(double))) + s[i];
       f[i] = F;
       if constexpr (SAVE) w[i] = F;
       const double ek = hf + cp * (T - kTref) - kRu * T * iW;
@@ -137,12 +138,13 @@ __device__ __forceinline__ void rhs_diff_cons(const DevMech& m, const MechLds& t
     if (r < ns) {
       const int q = (ROWS == 1 ? t.rspos : t.spos[r]);
       S.spc[LP + q] = 1e-6 * du[i] * (ROWS == 1 ? t.rinvW : t.invW[r]);
-      *acc_at<LP, double>((char*)S.spc, q * sizeof(double)) = 0.0;
+      acc_clear<LP, double>((char*)S.spc, q * sizeof(double));
     }
   }
   const double dlnT = log1p_small(dT * B.invT);
   const double dinvRT = -dT * (B.invRT * rcp(T1));
   char* rb = (char*)S.spc;
+  char* ab = acc_base<LP, double>(rb, lane);
   lds_sync();
   auto diff_rx = [&](int j, const uint2 o, double ca, double cb, double cc_, double cd) {
     const double2 bEf = t.bEf[j], bEr = t.bEr[j];
@@ -158,7 +160,7 @@ __device__ __forceinline__ void rhs_diff_cons(const DevMech& m, const MechLds& t
     const double pf = ca * cb, dpf = (ca + dca) * dcb + dca * cb;
     const double pr = cc_ * cd, dpr = (cc_ + dcc) * dcd + dcc * cd;
     const double dq = ((kj.x + dkf) * dpf + dkf * pf) - ((kj.y + dkr) * dpr + dkr * pr);
-    scatter_rate<LP, double>(rb, o, dq);
+    scatter_rate<LP, double>(ab, o, dq);
   };
   if constexpr (NIT > 0) {
     if (cc) {
@@ -187,7 +189,7 @@ __device__ __forceinline__ void rhs_diff_cons(const DevMech& m, const MechLds& t
     if (r < ns) {
       const double Wr = ROWS == 1 ? t.rW : t.W[r], iW = ROWS == 1 ? t.rinvW : t.invW[r];
       const double cp = ROWS == 1 ? t.rcp : t.cp[r], hf = ROWS == 1 ? t.rhf : t.hf[r];
-      const double dF = Wr * (1e6 * *acc_at<LP, double>(rb, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(double)));
+      const double dF = Wr * (1e6 * acc_sum<LP, double>(rb, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(double)));
       df[i] = dF;
       const double cv = cp - kRu * iW;
       const double ek = hf + cp * (T - kTref) - kRu * T * iW, dek = cv * dT;

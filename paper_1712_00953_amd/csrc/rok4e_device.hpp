@@ -332,21 +332,57 @@ __device__ __forceinline__ double rcp(double x) {
 
 // Per-segment LDS scratch of the right-hand side.  spc holds the concentrations of the
 // base state and their increments (difference evaluation), LP entries each in the rate
-// type, followed by LP FP64 production accumulators: species k sits at spc[k],
-// spc[LP + k] and acc(k) (consecutive species fall in different LDS banks).  The
-// accumulators are FP64 in both precisions.  Entry ns is the absent reaction slot:
-// concentration 1, increment 0, accumulator never read.
+// type, followed by the FP64 production accumulators (FP64 in both precisions): species k
+// sits at spc[k], spc[LP + k] and acc(k) (consecutive species fall in different LDS
+// banks).  In the mixed form the accumulators come in two copies, LP + 8 entries apart
+// (half the banks over): the reaction lanes of even index add into the first, those of
+// odd index into the second, and a species' production is the sum of its two entries.
+// Two lanes of one accumulate instruction that add into the same address are serialised
+// by the LDS at a cost well above that of a bank conflict, and with the copies
+// neighbouring lanes never do.  The FP64 layout keeps one copy: the second does not fit
+// beside three blocks per CU.  Entry ns is the absent reaction slot: concentration 1,
+// increment 0, accumulators never read.
 template <class RT>
 struct RhsLds {
-  RT* spc;                        // [2][LP] rate type, then double [LP]
+  RT* spc;                        // [2][LP] rate type, then double [LP] (x2 + 8 mixed)
   typename Pair2<RT>::type* k;    // [NRP] (k_f, k_r) of the base state
 };
 
-// Accumulator of the species at byte offset off (species x sizeof(RT)) of the concentration
-// array that starts at rb.
+// Accumulator copies of the layout (2 in the mixed form, 1 in FP64) and the byte
+// distance between them.
+template <class RT>
+constexpr int acc_copies() { return sizeof(RT) == 4 ? 2 : 1; }
+template <int LP>
+constexpr unsigned acc_copy_bytes() { return (LP + 8) * sizeof(double); }
+
+// Accumulator (first copy) of the species at byte offset off (species x sizeof(RT)) of the
+// concentration array that starts at rb.
 template <int LP, class RT>
 __device__ __forceinline__ double* acc_at(char* rb, unsigned off) {
   return (double*)(rb + 2 * LP * sizeof(RT) + off * (sizeof(double) / sizeof(RT)));
+}
+
+// Clears the accumulator copies of a species.
+template <int LP, class RT>
+__device__ __forceinline__ void acc_clear(char* rb, unsigned off) {
+  double* a = acc_at<LP, RT>(rb, off);
+  a[0] = 0.0;
+  if constexpr (acc_copies<RT>() == 2) a[acc_copy_bytes<LP>() / sizeof(double)] = 0.0;
+}
+
+// Production sum of a species: first copy (+ second copy).
+template <int LP, class RT>
+__device__ __forceinline__ double acc_sum(char* rb, unsigned off) {
+  const double* a = acc_at<LP, RT>(rb, off);
+  if constexpr (acc_copies<RT>() == 2) return a[0] + a[acc_copy_bytes<LP>() / sizeof(double)];
+  return a[0];
+}
+
+// Base address for this lane's accumulates (its copy); concentrations are read from rb.
+template <int LP, class RT>
+__device__ __forceinline__ char* acc_base(char* rb, int lane) {
+  if constexpr (acc_copies<RT>() == 2) return rb + ((lane & 1) ? acc_copy_bytes<LP>() : 0u);
+  return rb;
 }
 
 // Cell-uniform quantities of a base evaluation f(u), kept for the difference evaluation.
@@ -388,8 +424,9 @@ __device__ __forceinline__ void lds_add(RT* p, RT v) {
 }
 
 // Adds -q to the accumulators of the reactants and +q to those of the products of one
-// reaction: a repeated species receives the term twice, a species on both sides -q and
-// +q.  An absent slot adds into the accumulator of entry ns, which is never read.
+// reaction (rb: the lane's accumulator base, acc_base): a repeated species receives the
+// term twice, a species on both sides -q and +q.  An absent slot adds into the
+// accumulator of entry ns, which is never read.
 template <int LP, class RT>
 __device__ __forceinline__ void scatter_rate(char* rb, uint2 o, RT qr) {
   const double q = (double)qr;
@@ -431,13 +468,14 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
     if (r < ns) {
       const int q = (ROWS == 1 ? t.rspos : t.spos[r]);
       S.spc[q] = (RT)(1e-6 * rho * u[s] * (ROWS == 1 ? t.rinvW : t.invW[r]));
-      *acc_at<LP, RT>((char*)S.spc, q * sizeof(RT)) = 0.0;
+      acc_clear<LP, RT>((char*)S.spc, q * sizeof(RT));
     }
   }
   const double lnT = log(T);
   const double invT = rcp(T);
   const double invRT = invT * (1.0 / kRu);
   char* rb = (char*)S.spc;
+  char* ab = acc_base<LP, RT>(rb, lane);
   lds_sync();
 #pragma unroll ROK4E_RX_UNROLL
   for (int j = lane; j < m.nr; j += L) {
@@ -448,14 +486,14 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
     const uint2 o = t.rxo[j];
     const RT pf = *(const RT*)(rb + (o.x & 0xFFFFu)) * *(const RT*)(rb + (o.x >> 16));
     const RT pr = *(const RT*)(rb + (o.y & 0xFFFFu)) * *(const RT*)(rb + (o.y >> 16));
-    scatter_rate<LP, RT>(rb, o, kf * pf - kr * pr);
+    scatter_rate<LP, RT>(ab, o, kf * pf - kr * pr);
   }
   lds_sync();
   double ph[ROWS];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const RT wk = r < ns ? (RT)(1e6 * *acc_at<LP, RT>((char*)S.spc, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(RT))) : (RT)0;
+    const RT wk = r < ns ? (RT)(1e6 * acc_sum<LP, RT>((char*)S.spc, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(RT))) : (RT)0;
     w[s] = wk;
     f[s] = (double)((RT)(ROWS == 1 ? t.rW : t.W[r]) * wk * (RT)invrho);
     const RT hk = (RT)((ROWS == 1 ? t.rhf : t.hf[r]) + (ROWS == 1 ? t.rcp : t.cp[r]) * (T - kTref));
@@ -526,12 +564,13 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
     if (r < ns) {
       const int q = (ROWS == 1 ? t.rspos : t.spos[r]);
       S.spc[LP + q] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * (ROWS == 1 ? t.rinvW : t.invW[r]));
-      *acc_at<LP, RT>((char*)S.spc, q * sizeof(RT)) = 0.0;
+      acc_clear<LP, RT>((char*)S.spc, q * sizeof(RT));
     }
   }
   const double dlnT = log1p_small(dT * B.invT);
   const double dinvRT = -dT * (B.invRT * invT1);
   char* rb = (char*)S.spc;
+  char* ab = acc_base<LP, RT>(rb, lane);
   lds_sync();
   // one reaction: rate-constant increments, concentration products with increments,
   // d q, scattered
@@ -560,7 +599,7 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
     const RT pf = ca * cb, dpf = (ca + dca) * dcb + dca * cb;
     const RT pr = cc_ * cd, dpr = (cc_ + dcc) * dcd + dcc * cd;
     const RT dq = ((kf + dkf) * dpf + dkf * pf) - ((kr + dkr) * dpr + dkr * pr);
-    scatter_rate<LP, RT>(rb, o, dq);
+    scatter_rate<LP, RT>(ab, o, dq);
   };
   if constexpr (NIT > 0) {
     if (cc) {
@@ -584,7 +623,7 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const double dw = r < ns ? 1e6 * *acc_at<LP, RT>((char*)S.spc, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(RT)) : 0.0;
+    const double dw = r < ns ? 1e6 * acc_sum<LP, RT>((char*)S.spc, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(RT)) : 0.0;
     const double wk = (double)w[s];
     df[s] = (ROWS == 1 ? t.rW : t.W[r]) * (dw * invrho1 - wk * drho * B.invrho * invrho1);
     const double hk = (ROWS == 1 ? t.rhf : t.hf[r]) + (ROWS == 1 ? t.rcp : t.cp[r]) * (T - kTref), dhk = (ROWS == 1 ? t.rcp : t.cp[r]) * dT;

@@ -11,7 +11,9 @@
 //
 // Cost model: the LDS serves an instruction in passes of G lanes over B four-byte banks;
 // a pass costs the largest number of distinct addresses that fall in one bank, and an
-// accumulate pass at least the largest number of lanes adding into one address.  The
+// accumulate pass at least the largest number of lanes adding into one address.  With two
+// accumulator copies (the mixed layout) lanes of even and odd index accumulate into
+// different copies, so their addresses differ for the same species.  The
 // search minimises the sum over the two geometries (B, G) = (32, 16) and (64, 32) by
 // simulated annealing over swaps of two reaction positions or two species positions,
 // with a fixed seed (the placement is a deterministic function of the mechanism).
@@ -32,15 +34,17 @@ struct Placement {
 class PlacementSearch {
  public:
   // slots: [nr][4] species of reactant 0, 1, product 0, 1 (ns for an absent slot);
-  // L: lanes per segment; word: bytes of one concentration entry (8 or 4).
-  PlacementSearch(int ns, int nr, const std::vector<int>& slots, int L, int word)
-      : ns_(ns), nr_(nr), L_(L), word_(word), slots_(slots) {
+  // L: lanes per segment; word: bytes of one concentration entry (8 or 4); copy_dw:
+  // distance in four-byte words between the two accumulator copies (0: one copy).
+  PlacementSearch(int ns, int nr, const std::vector<int>& slots, int L, int word, int copy_dw)
+      : ns_(ns), nr_(nr), L_(L), word_(word), copy_dw_(copy_dw), slots_(slots) {
     order_.resize(nr);
     for (int j = 0; j < nr; ++j) order_[j] = j;
     pos_.resize(ns + 1);
     for (int k = 0; k <= ns; ++k) pos_[k] = k;
-    stamp_.assign(ns + 1, 0);
-    mult_.assign(ns + 1, 0);
+    stamp_.assign(2 * (ns + 1), 0);
+    mult_.assign(2 * (ns + 1), 0);
+    rstamp_.assign(ns + 1, 0);
     n_it_ = (nr + L - 1) / L;
     for (int g = 0; g < 2; ++g) {
       const int G = std::min(kGeom[g].G, L);
@@ -137,15 +141,20 @@ class PlacementSearch {
             const int p = it * L_ + l;
             if (p >= nr_) break;
             const int a = pos_[slots_[order_[p] * 4 + sl]];
-            if (stamp_[a] != gen_) {   // first lane with this address
-              stamp_[a] = gen_;
-              mult_[a] = 1;
+            if (rstamp_[a] != gen_) {   // first lane reading this concentration
+              rstamp_[a] = gen_;
               rmax = std::max(rmax, ++rload[(a * words) % B]);
-              bmax = std::max(bmax, ++aload[(a * 2) % B]);
-            } else {
-              ++mult_[a];
             }
-            amax = std::max(amax, mult_[a]);
+            const int c = copy_dw_ ? (l & 1) : 0;   // accumulator copy of this lane
+            const int ka = a + c * (ns_ + 1);
+            if (stamp_[ka] != gen_) {   // first lane adding into this address
+              stamp_[ka] = gen_;
+              mult_[ka] = 1;
+              bmax = std::max(bmax, ++aload[(a * 2 + c * copy_dw_) % B]);
+            } else {
+              ++mult_[ka];
+            }
+            amax = std::max(amax, mult_[ka]);
           }
           c += rmax + std::max(amax, bmax);
         }
@@ -154,10 +163,10 @@ class PlacementSearch {
     return c;
   }
 
-  int ns_, nr_, L_, word_, n_it_;
+  int ns_, nr_, L_, word_, copy_dw_, n_it_;
   int groups_[2];
   std::vector<int> slots_, order_, pos_;
-  mutable std::vector<int> stamp_, mult_;
+  mutable std::vector<int> stamp_, mult_, rstamp_;
   mutable int gen_ = 0;
   std::vector<long> cost_;
   long total_;
