@@ -205,3 +205,55 @@ def test_conservative_small_layouts(R, orc, lanes):
     print(f"[cons L={lanes} cfg{cfg}] rel={got:.3e} twin={env:.3e}", flush=True)
     assert got <= max(1e-10, 4 * env)
     assert np.mean((g[2] == o[2])[ok] & (g[3] == o[3])[ok]) >= 0.98
+
+
+def test_conservative_fixed_steps_parity(R, orc):
+    # three equal steps without error control: the stage arithmetic alone
+    import torch
+    w, U, S = cons_case(orc, 2, 64)
+    ns = w.mech.n_species
+    o = orc.integrate_cons(w.mech, U, w.dt, w.rtol, w.atol, w.M, S=S, fixed_steps=3)
+    tw = orc.integrate_cons(w.mech, U, w.dt, w.rtol, w.atol, w.M, S=S, fixed_steps=3, fma=True)
+    m = R.Mech(w.mech, M=w.M, fixed_steps=3)
+    Ud = torch.tensor(U, dtype=torch.float64, device="cuda:0")
+    Sd = torch.tensor(S, dtype=torch.float64, device="cuda:0")
+    Ta = torch.full((64,), float("nan"), dtype=torch.float64, device="cuda:0")
+    m.integrate_conservative(Ud, w.dt, w.rtol, w.atol, S=Sd, T_aux=Ta)
+    torch.cuda.synchronize()
+    m.close()
+    g = (Ud.cpu().numpy(), Ta.cpu().numpy())
+    env, got = rel_max(tw, o, ns), rel_max(g, o, ns)
+    print(f"\n[cons fixed] rel={got:.3e} twin={env:.3e}", flush=True)
+    assert np.all(o[2] == 3)
+    assert got <= max(1e-10, 4 * env)
+
+
+def test_conservative_graph_replays_match_eager(R, orc):
+    """rok4e_integrate_conservative captured in a HIP graph (queue reset kernel and the
+    integrator): replays on fresh inputs copied in eagerly between them equal the eager
+    call bit for bit."""
+    import torch
+    w, U, S = cons_case(orc, 2, 256)
+    m = R.Mech(w.mech, M=w.M)
+    m.reserve(256)
+    U0 = torch.tensor(U, dtype=torch.float64, device="cuda:0")
+    Sd = torch.tensor(S, dtype=torch.float64, device="cuda:0")
+    Ue, Te = U0.clone(), torch.zeros(256, dtype=torch.float64, device="cuda:0")
+    m.integrate_conservative(Ue, w.dt, w.rtol, w.atol, S=Sd, T_aux=Te)
+    torch.cuda.synchronize()
+    Ug, Tg = U0.clone(), torch.zeros(256, dtype=torch.float64, device="cuda:0")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            m.integrate_conservative(Ug, w.dt, w.rtol, w.atol, S=Sd, T_aux=Tg)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        Ug.copy_(U0)
+        Tg.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Ug, Ue) and torch.equal(Tg, Te), f"replay {rep}"
+    m.close()
