@@ -187,10 +187,11 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* mech, double* Y, double* T, 
  * exact solution.  The chemistry is that of a constant-volume reactor (c_k = rho Y_k /
  * W_k).  T_aux[n_cells] (device, may be NULL) receives the auxiliary temperature at dt.
  * A cell with non-finite input, rho <= 0, rho c_v <= 0 or a temperature <= 0 keeps U
- * (and its T_aux entry) and reports status 3.  Persistent schedule, FP64, ROK4E only,
- * and a layout of at least ns + 6 rows (lanes_per_cell x slots); ROK4E_ENOTSUP
- * otherwise.  Cells are handed out in array order; per-cell statistics as for
- * rok4e_integrate. */
+ * (and its T_aux entry) and reports status 3.  Persistent schedule, FP64, ROK4E only
+ * (ROK4E_ENOTSUP otherwise).  The handle's lane layout is used when it holds ns + 6
+ * rows; otherwise the call uses the smallest layout that does (same options) and builds
+ * its table image on first use, which returns ROK4E_ECAPTURE inside a stream capture.
+ * Cells are handed out in array order; per-cell statistics as for rok4e_integrate. */
 int rok4e_integrate_conservative(int64_t n_cells, rok4e_mech* mech, double* U, const double* S,
                                  double* T_aux, double dt, double rtol, double atol, void* stream);
 

@@ -359,6 +359,12 @@ struct rok4e_mech {
   int image_key = -1;
   DevMech dm{};
   void* d_image = nullptr;
+  // layout and image of the conservative-variable form when the current layout holds
+  // fewer than ns + 6 rows
+  const Variant* cons_var = nullptr;
+  int cons_image_key = -1;
+  DevMech cons_dm{};
+  void* d_cons_image = nullptr;
   unsigned int* d_queue = nullptr;
   // per-cell workspace
   int64_t cap = 0;
@@ -398,9 +404,10 @@ bool options_ok(const rok4e_options& o) {
   return true;
 }
 
-// Smallest instantiated variant that holds ns+1 rows and M Krylov vectors.
-const Variant* pick_variant(int ns, const rok4e_options& o) {
-  const int N = ns + 1;
+// Smallest instantiated variant that holds ns + extra rows (the reactor state: extra = 1)
+// and M Krylov vectors.
+const Variant* pick_variant(int ns, const rok4e_options& o, int extra = 1) {
+  const int N = ns + extra;
   const Variant* best = nullptr;
   for (const Variant& v : kVariants) {
     if (v.prec != o.precision || v.mmax < o.M || v.L * v.rows < N) continue;
@@ -454,11 +461,12 @@ constexpr long kPlacementSteps = 60000;
 
 // Builds (or reuses) the table image for the handle's current layout and rate type; see
 // DevMech.
-int ensure_image(rok4e_mech* m) {
-  const int lp = m->var->L * m->var->rows;
-  const int rb = rate_bytes(m->var->prec);
+// Builds the table image of layout var into *d_image / *dm (kept while *image_key matches).
+int build_image(rok4e_mech* m, const Variant* var, DevMech* dm, void** d_image, int* image_key) {
+  const int lp = var->L * var->rows;
+  const int rb = rate_bytes(var->prec);
   const int key = lp * 64 + rb;
-  if (m->image_key == key && m->d_image) return ROK4E_OK;
+  if (*image_key == key && *d_image) return ROK4E_OK;
   const int ns = m->ns, nr = m->nr;
   const int nrp = n_rx_padded(nr);
   // placement of reactions on (iteration, lane) positions and of species in LDS
@@ -467,7 +475,7 @@ int ensure_image(rok4e_mech* m) {
     const int sl[4] = {m->reac[2 * j], m->reac[2 * j + 1], m->prod[2 * j], m->prod[2 * j + 1]};
     for (int a = 0; a < 4; ++a) slots[4 * j + a] = sl[a] < 0 ? ns : sl[a];
   }
-  PlacementSearch search(ns, nr, slots, m->var->L, rb, rb == 4 ? 2 * lp + 16 : 0);
+  PlacementSearch search(ns, nr, slots, var->L, rb, rb == 4 ? 2 * lp + 16 : 0);
   const Placement pl = search.run(kPlacementSteps, 0x5eed0000ull + (uint64_t)key);
   const int off_spec = al16(3 * nrp * 16);
   const int off_rxo = al16(off_spec + 4 * lp * 8);
@@ -514,15 +522,18 @@ int ensure_image(rok4e_mech* m) {
       be[4 * q + 3] = (float)m->par[5 * nr + j];
     }
   }
-  if (m->d_image) (void)hipFree(m->d_image);
-  m->d_image = nullptr;
-  hipError_t e = hipMalloc(&m->d_image, bytes);
-  if (e == hipSuccess) e = hipMemcpy(m->d_image, img.data(), bytes, hipMemcpyHostToDevice);
+  if (*d_image) (void)hipFree(*d_image);
+  *d_image = nullptr;
+  *image_key = -1;
+  hipError_t e = hipMalloc(d_image, bytes);
+  if (e == hipSuccess) e = hipMemcpy(*d_image, img.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e);
-  m->dm = DevMech{ns, nr, nrp, lp, off_spec, off_rxo, off_spos, off_bE32, bytes, (const int4*)m->d_image};
-  m->image_key = key;
+  *dm = DevMech{ns, nr, nrp, lp, off_spec, off_rxo, off_spos, off_bE32, bytes, (const int4*)*d_image};
+  *image_key = key;
   return ROK4E_OK;
 }
+
+int ensure_image(rok4e_mech* m) { return build_image(m, m->var, &m->dm, &m->d_image, &m->image_key); }
 
 struct LaunchShape {
   int block, grid, segs_per_block, lds;
@@ -532,15 +543,16 @@ struct LaunchShape {
 // fit), as many blocks per CU as occupancy allows for a persistent launch, never more
 // segments than cells.
 int shape_for(const rok4e_mech* m, const SegLayout& sl, int64_t n_cells, const void* kernel,
-              bool persistent, LaunchShape* out) {
-  const Variant& v = *m->var;
+              bool persistent, LaunchShape* out, const Variant* var = nullptr, const DevMech* dmp = nullptr) {
+  const Variant& v = var ? *var : *m->var;
+  const DevMech& dm = dmp ? *dmp : m->dm;
   int wpb = m->opt.waves_per_block > 0 ? m->opt.waves_per_block : 4;
   const int segs_per_wave = 64 / v.L;
-  while (wpb > 1 && (size_t)(m->dm.image_bytes + wpb * segs_per_wave * sl.bytes) > m->lds_per_block_max) --wpb;
+  while (wpb > 1 && (size_t)(dm.image_bytes + wpb * segs_per_wave * sl.bytes) > m->lds_per_block_max) --wpb;
   LaunchShape s{};
   s.block = 64 * wpb;
   s.segs_per_block = wpb * segs_per_wave;
-  s.lds = m->dm.image_bytes + s.segs_per_block * sl.bytes;
+  s.lds = dm.image_bytes + s.segs_per_block * sl.bytes;
   if ((size_t)s.lds > m->lds_per_block_max) return ROK4E_ENOTSUP;
   const int64_t need = (n_cells + s.segs_per_block - 1) / s.segs_per_block;
   int per_cu = 1;
@@ -704,7 +716,7 @@ int rok4e_mech_destroy(rok4e_mech* m) {
   (void)hipGetDevice(&dev);
   (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
-  void* bufs[] = {m->d_image, m->d_queue, m->d_acc, m->d_rej, m->d_status, m->d_order, m->d_bins,
+  void* bufs[] = {m->d_image, m->d_cons_image, m->d_queue, m->d_acc, m->d_rej, m->d_status, m->d_order, m->d_bins,
                   m->d_st, m->d_fnq, m->d_H,
                   m->d_act[0], m->d_act[1], m->d_cnt};
   for (void* b : bufs) (void)hipFree(b);
@@ -874,23 +886,41 @@ int rok4e_integrate_conservative(int64_t n_cells, rok4e_mech* m, double* U, cons
       !std::isfinite(atol))
     return ROK4E_EINVAL;
   if (m->opt.precision != ROK4E_FP64 || m->opt.method != ROK4E_METHOD_ROK4E ||
-      m->opt.scheduling != ROK4E_PERSISTENT || !m->var->integrate_cons ||
-      m->var->L * m->var->rows < m->ns + 6)
+      m->opt.scheduling != ROK4E_PERSISTENT)
     return ROK4E_ENOTSUP;
   if (n_cells == 0) return ROK4E_OK;
   hipStream_t st = (hipStream_t)stream;
+  // the handle's layout if it holds the ns + 6 rows, else the smallest one that does
+  // (same options), with its own table image
+  const Variant* var = m->var;
+  const DevMech* dm = &m->dm;
+  if (var->L * var->rows < m->ns + 6) {
+    var = pick_variant(m->ns, m->opt, 6);
+    if (!var) return ROK4E_ENOTSUP;
+    if (m->cons_var != var || m->cons_image_key < 0) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return ROK4E_ECAPTURE;
+      m->cons_image_key = -1;
+      const int rc = build_image(m, var, &m->cons_dm, &m->d_cons_image, &m->cons_image_key);
+      if (rc) return rc;
+      m->cons_var = var;
+    }
+    dm = &m->cons_dm;
+  }
+  if (!var->integrate_cons) return ROK4E_ENOTSUP;
   int rc = ensure_workspace(m, n_cells, st);
   if (rc) return rc;
-  const SegLayout sl = seg_layout(m->nr, *m->var);
+  const SegLayout sl = seg_layout(m->nr, *var);
   Launch P = base_launch(m, n_cells, U, T_aux, nullptr, S, sl);
   P.dt = dt;
   P.rtol = rtol;
   P.atol = atol;
   LaunchShape sh;
-  rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate_cons, true, &sh);
+  rc = shape_for(m, sl, n_cells, (const void*)var->integrate_cons, true, &sh, var, dm);
   if (rc) return rc;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
-  hipLaunchKernelGGL(m->var->integrate_cons, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
+  hipLaunchKernelGGL(var->integrate_cons, dim3(sh.grid), dim3(sh.block), sh.lds, st, *dm, P);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e);
   m->last_n = n_cells;

@@ -257,3 +257,49 @@ def test_conservative_graph_replays_match_eager(R, orc):
         torch.cuda.synchronize()
         assert torch.equal(Ug, Ue) and torch.equal(Tg, Te), f"replay {rep}"
     m.close()
+
+
+def test_conservative_on_a_handle_whose_layout_is_too_small(R, orc):
+    # 60 species: the reactor state (61 rows) fits the handle's one-slot 64-lane layout,
+    # the conservative state (66 rows) does not, so the call runs on the two-slot layout
+    # with its own table image; the handle's reactor results are unaffected
+    import torch
+    mech = synth.make_mechanism(60, 300, 4, 777, a_scale=1e-8)
+    st = synth.states_flame(mech, 16, 8, 778)
+    n = st.n_cells
+    ns = mech.n_species
+    rng = np.random.default_rng(5)
+    vel = 50.0 * rng.standard_normal((3, n))
+    U = orc.cons_state(mech, st.Y, st.T, st.p, vel)
+    S = 1e3 * np.abs(U) * rng.standard_normal(U.shape)
+    dt, rtol, atol, M = 1e-5, 1e-6, 1e-12, 8
+    o = orc.integrate_cons(mech, U, dt, rtol, atol, M, S=S)
+    tw = orc.integrate_cons(mech, U, dt, rtol, atol, M, S=S, fma=True)
+    ok = o[4] == 0
+    m = R.Mech(mech, M=M)
+    assert m.get_options().lanes_per_cell == 64
+    Y0, T0, p0 = (torch.tensor(a, dtype=torch.float64, device="cuda:0") for a in (st.Y, st.T, st.p))
+    Ya, Ta_ = Y0.clone(), T0.clone()
+    m.integrate(Ya, Ta_, p0, dt, rtol, atol)
+    Ud = torch.tensor(U, dtype=torch.float64, device="cuda:0")
+    Sd = torch.tensor(S, dtype=torch.float64, device="cuda:0")
+    Ta = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0")
+    m.integrate_conservative(Ud, dt, rtol, atol, S=Sd, T_aux=Ta)
+    acc = torch.zeros(n, dtype=torch.int32)
+    rej = torch.zeros(n, dtype=torch.int32)
+    sta = torch.zeros(n, dtype=torch.int32)
+    m.cell_stats(acc, rej, sta)
+    Yb, Tb = Y0.clone(), T0.clone()
+    m.integrate(Yb, Tb, p0, dt, rtol, atol)
+    torch.cuda.synchronize()
+    m.close()
+    assert torch.equal(Ya, Yb) and torch.equal(Ta_, Tb)
+    g = (Ud.cpu().numpy(), Ta.cpu().numpy(), acc.numpy(), rej.numpy(), sta.numpy())
+    np.testing.assert_array_equal(g[4], o[4])
+    assert ok.sum() > 0
+    sub = lambda r: (r[0][:, ok], r[1][ok], r[2][ok], r[3][ok])
+    env, got = rel_max(sub(tw), sub(o), ns), rel_max(sub(g), sub(o), ns)
+    print(f"\n[cons 60sp two-slot] cells {n}, refused {int((~ok).sum())}, rel={got:.3e} twin={env:.3e}",
+          flush=True)
+    assert got <= max(1e-10, 4 * env)
+    assert np.mean((g[2] == o[2])[ok] & (g[3] == o[3])[ok]) >= 0.98
