@@ -569,3 +569,24 @@ def test_full_batch_mixed_sampled(R, orc):
     # are sanity bars
     assert d["rel_vs_oracle"] <= 1e-4
     assert d["rel_vs_fp64_same_steps"] <= 1e-3 and d["p99_vs_fp64"] <= 1e-4
+
+
+def test_full_krylov_space_parity(R, orc):
+    """M = 16 on the 9-species workload (N = 10 state rows): the Krylov space fills the
+    whole state space (M_eff = N, or less where the Arnoldi process stops early), the
+    case in which ROK4E is the dense Rosenbrock method; FP64 bar as above."""
+    w = synth.workload(1, a_scale=A_SCALE, n_cells=256)
+    st = w.states
+    M = 16
+    o = orc.integrate(w.mech, st.Y, st.T, st.p, w.dt, w.rtol, w.atol, M)
+    tw = orc.integrate(w.mech, st.Y, st.T, st.p, w.dt, w.rtol, w.atol, M, fma=True)
+    m = R.Mech(w.mech, M=M, max_attempts=MAX_ATT)
+    g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    m.close()
+    env, got = relative(tw, o), relative(g, o)
+    match = (g[2] == o[2]) & (g[3] == o[3])
+    twin_match = (tw[2] == o[2]) & (tw[3] == o[3])
+    _report("full krylov cfg1 M=16", dict(rel=got, twin=env, match=float(match.mean())))
+    assert np.all(g[4] == 0) and np.all(o[4] == 0)
+    assert got <= max(1e-10, 4 * env)
+    assert match[twin_match].mean() >= match_floor(twin_match.mean(), st.n_cells)
