@@ -322,12 +322,13 @@ def test_many_reactions_fall_back_to_lds_reads(R, orc):
     m.close()
 
 
-@pytest.mark.parametrize("cfg,n", [(1, 300), (3, 512)])
-def test_per_attempt_schedule_is_bitwise_identical(R, cfg, n):
+@pytest.mark.parametrize("cfg,n,prec", [(1, 300, 0), (3, 512, 0), (3, 256, 1)])
+def test_per_attempt_schedule_is_bitwise_identical(R, cfg, n, prec):
     """One launch per attempt with the cell state carried in device memory performs the
     same arithmetic as the persistent kernel, and the persistent queue's order (hottest
     cells first, or array order) does not touch a cell's arithmetic: identical states and
-    counts, also for an invalid cell, the attempt limit and fixed steps."""
+    counts, also for an invalid cell, the attempt limit and fixed steps; in both
+    precisions."""
     w = synth.workload(cfg, a_scale=A_SCALE)
     idx = synth.stratified_sample(w.states.T, n, 300 + cfg)
     st = w.states.subset(idx)
@@ -338,7 +339,7 @@ def test_per_attempt_schedule_is_bitwise_identical(R, cfg, n):
         outs = []
         for sched, order in ((R.PERSISTENT, R.ORDER_HOT_FIRST), (R.PERSISTENT, R.ORDER_ARRAY),
                              (R.PER_ATTEMPT, R.ORDER_HOT_FIRST)):
-            m = R.Mech(w.mech, M=w.M, scheduling=sched, cell_order=order, **kw)
+            m = R.Mech(w.mech, M=w.M, scheduling=sched, cell_order=order, precision=prec, **kw)
             outs.append(gpu_integrate(m, st, w.dt, w.rtol, w.atol))
             m.close()
         assert outs[0][4][3] == 3
@@ -367,16 +368,19 @@ def test_cell_order_is_bitwise_neutral(R):
         np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("n", [400, 32768])
-def test_graph_capture_replays_match_eager(R, n):
+@pytest.mark.parametrize("n,prec", [(400, 0), (32768, 0), (32768, 1)])
+def test_graph_capture_replays_match_eager(R, n, prec):
     """The persistent launch (queue reset kernel + integrator, no memset node; for the
     larger batch also the four kernels that order the queue hottest first) captured in a
     HIP graph: several replays, each on fresh inputs copied in eagerly between them,
     equal the eager call bit for bit."""
     import torch
-    w = synth.workload(1, a_scale=A_SCALE, n_cells=n)
+    # the 9-species workload has 1,024 cells; the larger case takes the flame slice, whose
+    # 32,768 cells are enough (eight per segment in flight) for the queue order kernels
+    w = synth.workload(1 if n <= 1024 else 2, a_scale=A_SCALE, n_cells=n)
     st = w.states
-    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    assert st.n_cells == n
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT, precision=prec)
     m.reserve(st.n_cells)
     Y0, T0, p = dev_state(st)
     Ye, Te = Y0.clone(), T0.clone()
