@@ -400,7 +400,9 @@ def run_study(R, torch, synth, n_cells=16384, t_end=1e-5, rtol=1e-4, atol=1e-8):
 
 
 def run_cpu_baseline(w, target_s=10.0):
-    """The oracle on a uniformly drawn sample of the batch, all host threads."""
+    """The oracle on a uniformly drawn sample of the batch, all host threads.  Returns the
+    baseline record and the oracle's results on the sample (indices, Y, T, accepted,
+    rejected, status) for the parity check of the GPU result."""
     from oracle import oracle as O
     st = w.states
     threads = len(os.sched_getaffinity(0))
@@ -413,11 +415,36 @@ def run_cpu_baseline(w, target_s=10.0):
     idx = np.sort(np.random.default_rng(78).choice(st.n_cells, n, replace=False))
     sub = st.subset(idx)
     t0 = time.perf_counter()
-    O.integrate(w.mech, sub.Y, sub.T, sub.p, w.dt, w.rtol, w.atol, w.M, nthreads=threads)
+    res = O.integrate(w.mech, sub.Y, sub.T, sub.p, w.dt, w.rtol, w.atol, w.M, nthreads=threads)
     el = time.perf_counter() - t0
-    return dict(value=n / el, unit="cell-integrations/s", cores=threads, kind="oracle",
-                sample=f"{n} cells drawn uniformly (seed 78) from the {st.n_cells}-cell batch, "
-                       f"{el:.1f} s wall on {threads} threads of {cpu_model()}")
+    rec = dict(value=n / el, unit="cell-integrations/s", cores=threads, kind="oracle",
+               sample=f"{n} cells drawn uniformly (seed 78) from the {st.n_cells}-cell batch, "
+                      f"{el:.1f} s wall on {threads} threads of {cpu_model()}")
+    return rec, (idx, *res)
+
+
+def sample_parity(gpu, oracle_sample, rtol, atol, bar=1e-10, floor=1e-14):
+    """FP64 GPU result of the full batch against the oracle on its timing sample:
+    relative error on species above `floor` and on T, graded on the cells whose
+    accept/reject counts equal the oracle's (several step sequences are correct; the
+    others are counted and their tolerance-normalised difference reported), and the
+    cells above the bar."""
+    idx, Yo, To, ao, ro, so = oracle_sample
+    (Yg, Tg), (ag, rg) = gpu["final_state"], gpu["cell_counts"]
+    Yg, Tg, ag, rg = Yg[:, idx], Tg[idx], ag[idx], rg[idx]
+    match = (ag == ao) & (rg == ro)
+    graded = np.maximum(np.abs(Yo), np.abs(Yg)) >= floor
+    rel = np.where(graded, np.abs(Yg - Yo) / np.maximum(np.abs(Yo), 1e-300), 0.0).max(axis=0)
+    rel = np.maximum(rel, np.abs(Tg - To) / np.abs(To))
+    norm = np.maximum((np.abs(Yg - Yo) / (atol + rtol * np.abs(Yo))).max(axis=0),
+                      np.abs(Tg - To) / (atol + rtol * np.abs(To)))
+    return {"cells": int(idx.size), "oracle_status_ok": int((so == 0).sum()),
+            "count_match_frac": float(match.mean()),
+            "max_rel_err_count_matched": float(rel[match].max()) if match.any() else None,
+            "p99_rel_err_count_matched": float(np.percentile(rel[match], 99)) if match.any() else None,
+            "cells_above_bar": int((rel[match] > bar).sum()), "bar": bar,
+            "max_norm_err_all": float(norm.max()),
+            "max_norm_err_count_mismatched": float(norm[~match].max()) if (~match).any() else None}
 
 
 def main():
@@ -495,10 +522,12 @@ def main():
         log("copy calibration: 1073741824 bytes read, 1073741824 bytes written "
             f"(last elementwise kernel), check {float(y[0] + evict[0])}")
         del x, y, evict
-    cpu = None
+    cpu = parity = None
     if not args.no_cpu_baseline:
-        cpu = run_cpu_baseline(w, args.cpu_seconds)
+        cpu, oracle_sample = run_cpu_baseline(w, args.cpu_seconds)
         log(f"cpu oracle: {cpu['value']:.4e} cells/s ({cpu['sample']})")
+        parity = sample_parity(fp64, oracle_sample, w.rtol, w.atol)
+        log(f"parity on the oracle sample: {parity}")
 
     traffic = load_traffic()
     achieved = fp64["tflops"]
@@ -573,6 +602,8 @@ def main():
         out["batch_size_curve"] = curve
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    if parity is not None:
+        out["parity_fp64_vs_oracle"] = parity
     print(json.dumps(out), flush=True)
 
 

@@ -1172,8 +1172,6 @@ int orc_rkdp_linear(int n, const double* A, const double* c, const orc_opts* o, 
   return 0;
 }
 
-// Dormand-Prince tableau in the order c2..c5, a21, a31, a32, a41..a43, a51..a54,
-// a61..a65, b1, b3..b6, bh1, bh3..bh7 (30 values; b2 = bh2 = b7 = 0), for the pins.
 // x = A^{-1} b through lu_factor / lu_solve (the projected solve of the stages), for
 // the pins; piv (m entries, may be null) receives the row chosen at each step.
 // Returns 0, or -1 for a zero pivot.
@@ -1188,6 +1186,8 @@ int orc_lu_solve(int m, const double* A, const double* b, double* x, int* piv) {
   return 0;
 }
 
+// Dormand-Prince tableau in the order c2..c5, a21, a31, a32, a41..a43, a51..a54,
+// a61..a65, b1, b3..b6, bh1, bh3..bh7 (30 values; b2 = bh2 = b7 = 0), for the pins.
 void orc_rkdp_coefficients(double* out) {
   const double v[30] = {dp::c2,  dp::c3,  dp::c4,  dp::c5,  dp::a21, dp::a31, dp::a32, dp::a41,
                         dp::a42, dp::a43, dp::a51, dp::a52, dp::a53, dp::a54, dp::a61, dp::a62,

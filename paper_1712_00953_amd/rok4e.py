@@ -113,8 +113,8 @@ def grid(nx, ny, nz, dx, vel, diff) -> Grid:
 def transport(g: Grid, n_species, Y, T, S, stream=None):
     """rok4e_transport: S[r * n + c] = T(U)_r for the state (Y, T) on grid g."""
     n = int(g.nx) * int(g.ny) * int(g.nz)
-    for t, cnt, name in ((Y, int(n_species) * n, "Y"), (T, n, "T"), (S, (int(n_species) + 1) * n, "S")):
-        _need(t, cnt, name)
+    for t, rows, name in ((Y, int(n_species), "Y"), (T, 1, "T"), (S, int(n_species) + 1, "S")):
+        _need(t, rows * n, name, rows=rows)
     _check(load().rok4e_transport(C.byref(g), int(n_species), _ptr(Y), _ptr(T), _ptr(S), _stream(stream)),
            "rok4e_transport")
 
@@ -144,10 +144,14 @@ def _ptr(t):
     return C.c_void_p(int(t))
 
 
-def _need(t, count, name, dtype="float64"):
+def _need(t, count, name, dtype="float64", rows=None):
     """Host-side check of a device operand before its pointer goes to a kernel: of the
     given dtype, contiguous, on a GPU, at least count elements (the kernels index it up
-    to there)."""
+    to there).  With rows, the operand is a structure-of-arrays block indexed
+    [r * n + c] for n = count / rows cells: it must have exactly the shape (rows, n),
+    or (n,) for rows == 1, or be flat with rows * n elements, so that a cell-major
+    [n, rows] tensor or a wider [rows, N > n] one is refused instead of being read with
+    the wrong stride."""
     if t is None:
         return
     if not hasattr(t, "data_ptr"):
@@ -157,6 +161,13 @@ def _need(t, count, name, dtype="float64"):
     if t.dtype != want or not t.is_cuda or not t.is_contiguous() or t.numel() < count:
         raise ValueError(f"{name}: need a contiguous {dtype} device tensor with >= {count} elements, "
                          f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+    if rows is not None:
+        n = count // rows if rows else 0
+        shape = tuple(t.shape)
+        ok = shape == (rows, n) or shape == (rows * n,) or (rows == 1 and shape == (n,))
+        if not ok:
+            raise ValueError(f"{name}: need shape ({rows}, {n}) (structure of arrays, stride {n}) "
+                             f"or a flat tensor of {rows * n} elements, got {shape}")
 
 
 def _stream(stream):
@@ -219,8 +230,8 @@ class Mech:
         to start the next call from out (rok4e_integrate_ex)."""
         n = int(T.shape[0]) if n_cells is None else int(n_cells)
         ns = self.n_species
-        for t, cnt, name in ((Y, ns * n, "Y"), (T, n, "T"), (p, n, "p"), (S, (ns + 1) * n, "S"), (h, n, "h")):
-            _need(t, cnt, name)
+        for t, rows, name in ((Y, ns, "Y"), (T, 1, "T"), (p, 1, "p"), (S, ns + 1, "S"), (h, 1, "h")):
+            _need(t, rows * n, name, rows=rows)
         rc = load().rok4e_integrate_ex(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(S), _ptr(h), float(dt),
                                        float(rtol), float(atol), _stream(stream))
         _check(rc, "rok4e_integrate")
@@ -233,8 +244,8 @@ class Mech:
         temperatures (rok4e_integrate_conservative)."""
         n = int(U.shape[-1]) if n_cells is None else int(n_cells)
         ns = self.n_species
-        for t, cnt, name in ((U, (ns + 5) * n, "U"), (S, (ns + 5) * n, "S"), (T_aux, n, "T_aux")):
-            _need(t, cnt, name)
+        for t, rows, name in ((U, ns + 5, "U"), (S, ns + 5, "S"), (T_aux, 1, "T_aux")):
+            _need(t, rows * n, name, rows=rows)
         rc = load().rok4e_integrate_conservative(n, self._h, _ptr(U), _ptr(S), _ptr(T_aux), float(dt),
                                                  float(rtol), float(atol), _stream(stream))
         _check(rc, "rok4e_integrate_conservative")
@@ -244,8 +255,8 @@ class Mech:
         """rok4e_tune: picks the fastest waves-per-block on a copy of this batch; returns
         (waves_per_block, ms)."""
         n = int(T.shape[0])
-        for t, cnt, name in ((Y, self.n_species * n, "Y"), (T, n, "T"), (p, n, "p")):
-            _need(t, cnt, name)
+        for t, rows, name in ((Y, self.n_species, "Y"), (T, 1, "T"), (p, 1, "p")):
+            _need(t, rows * n, name, rows=rows)
         wv, ms = C.c_int32(0), C.c_float(0.0)
         _check(load().rok4e_tune(n, self._h, _ptr(Y), _ptr(T), _ptr(p), float(dt), float(rtol), float(atol),
                                  C.byref(wv), C.byref(ms), _stream(stream)), "rok4e_tune")
@@ -255,18 +266,19 @@ class Mech:
     def rhs(self, Y, T, p, dY, dT, stream=None):
         n = int(T.shape[0])
         ns = self.n_species
-        for t, cnt, name in ((Y, ns * n, "Y"), (T, n, "T"), (p, n, "p"), (dY, ns * n, "dY"), (dT, n, "dT")):
-            _need(t, cnt, name)
+        for t, rows, name in ((Y, ns, "Y"), (T, 1, "T"), (p, 1, "p"), (dY, ns, "dY"), (dT, 1, "dT")):
+            _need(t, rows * n, name, rows=rows)
         _check(load().rok4e_rhs(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(dY), _ptr(dT), _stream(stream)),
                "rok4e_rhs")
 
     def arnoldi(self, Y, T, p, Q, H, Meff, stream=None):
         n = int(T.shape[0])
         ns, M = self.n_species, int(self.opts.M)
-        for t, cnt, name in ((Y, ns * n, "Y"), (T, n, "T"), (p, n, "p"), (Q, n * M * (ns + 1), "Q"),
-                             (H, n * M * M, "H")):
+        for t, rows, name in ((Y, ns, "Y"), (T, 1, "T"), (p, 1, "p")):
+            _need(t, rows * n, name, rows=rows)
+        for t, cnt, name in ((Q, n * M * (ns + 1), "Q"), (H, n * M * M, "H")):
             _need(t, cnt, name)
-        _need(Meff, n, "Meff", "int32")
+        _need(Meff, n, "Meff", "int32", rows=1)
         _check(load().rok4e_arnoldi(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(Q), _ptr(H), _ptr(Meff),
                                     _stream(stream)), "rok4e_arnoldi")
 
@@ -275,8 +287,8 @@ class Mech:
         work: a device tensor of at least workspace_bytes(grid) bytes."""
         n = int(grid.nx) * int(grid.ny) * int(grid.nz)
         ns = self.n_species
-        for t, cnt, name in ((Y, ns * n, "Y"), (T, n, "T"), (p, n, "p"), (src, (ns + 1) * n, "src")):
-            _need(t, cnt, name)
+        for t, rows, name in ((Y, ns, "Y"), (T, 1, "T"), (p, 1, "p"), (src, ns + 1, "src")):
+            _need(t, rows * n, name, rows=rows)
         _check(load().rok4e_split_step(self._h, C.byref(grid), int(scheme), _ptr(Y), _ptr(T), _ptr(p), _ptr(src),
                                        float(h), float(rtol), float(atol), int(nsub), _ptr(work),
                                        int(work.numel() * work.element_size()), _stream(stream)),

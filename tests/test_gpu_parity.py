@@ -483,6 +483,12 @@ def test_edge_cases(R, orc):
         m.integrate(Y, T, p, w.dt, w.rtol, w.atol, h=h[:2])
     with pytest.raises(ValueError):
         m.integrate(Y, T, p, w.dt, w.rtol, w.atol, h=h.float())
+    # state blocks in another layout than [rows, n] are refused by the binding: cell-major
+    # [n, ns], and a wider [ns, N] block with n_cells < N (the kernels index r * n + c)
+    with pytest.raises(ValueError):
+        m.integrate(Y.T.contiguous(), T, p, w.dt, w.rtol, w.atol)
+    with pytest.raises(ValueError):
+        m.integrate(Y, T, p, w.dt, w.rtol, w.atol, n_cells=2)
     m.set_options(M=w.M, method=R.METHOD_RKDP45)
     with pytest.raises(R.Rok4eError):
         m.integrate(Y, T, p, w.dt, w.rtol, w.atol, h=h)
@@ -515,7 +521,7 @@ def test_forcing_cancelling_f_is_identity(R, orc, cfg):
     m.close()
 
 
-@pytest.mark.parametrize("cfg,n_check", [(2, 96), (3, 96), (4, 48)])
+@pytest.mark.parametrize("cfg,n_check", [(2, 4096), (3, 1024), (4, 256)])
 def test_full_batch_sampled(R, orc, cfg, n_check):
     """The full batch in the benchmark's launch configuration; the oracle recomputes a
     seeded sample of cells one by one."""

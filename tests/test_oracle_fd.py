@@ -75,3 +75,73 @@ def test_rounding_envelope_is_within_tolerance(orc, cfg, n):
     assert match == 1.0
     assert rel.max() <= 1e-12
     assert e <= 1e-6
+
+
+# Sec. 4.3 defines the Jacobian-vector product as (f(u + delta v) - f(u)) / delta.  The
+# integrator (oracle and kernels alike) evaluates the numerator in difference form, an
+# evaluation of the same quotient in another rounding order.  These pins measure what that
+# choice does to the integrated result, against two other evaluations of J v: the literal
+# difference of two rounded FP64 right-hand sides (mode 3) and the exact product by a
+# complex step (mode 1), over a whole adaptive substep at rtol = 1e-6.
+JVP_MODES_CASES = [(1, 256), (2, 96), (4, 24)]
+
+
+@pytest.fixture(scope="module")
+def jvp_mode_runs(orc):
+    out = {}
+    for cfg, n in JVP_MODES_CASES:
+        w = synth.workload(cfg, a_scale=1e-8)
+        st = w.states.subset(synth.stratified_sample(w.states.T, n, 11))
+        runs = {}
+        for mode in (orc.JVP_FD, orc.JVP_COMPLEX, orc.JVP_FD_LITERAL):
+            for fma in (False, True):
+                runs[mode, fma] = orc.integrate(w.mech, st.Y, st.T, st.p, w.dt, w.rtol, w.atol, w.M,
+                                                jvp=mode, fma=fma)
+        out[cfg] = (w, runs)
+    return out
+
+
+def relative_max(a, b):
+    """Largest relative difference on species above 1e-14 and on T."""
+    g = np.maximum(np.abs(a[0]), np.abs(b[0])) >= 1e-14
+    return float(max((np.abs(a[0] - b[0])[g] / np.abs(b[0])[g]).max(), (np.abs(a[1] - b[1]) / b[1]).max()))
+
+
+@pytest.mark.parametrize("cfg", [c for c, _ in JVP_MODES_CASES])
+def test_jvp_reading_changes_the_result_far_below_the_tolerance(orc, jvp_mode_runs, cfg):
+    w, runs = jvp_mode_runs[cfg]
+    d = runs[orc.JVP_FD, False]
+    for mode in (orc.JVP_COMPLEX, orc.JVP_FD_LITERAL):
+        o = runs[mode, False]
+        assert np.all(o[4] == 0) and np.all(d[4] == 0)
+        norm = normalized_error(d[:2], o[:2], w.rtol, w.atol)
+        rel = relative_max(d, o)
+        match = np.mean((d[2] == o[2]) & (d[3] == o[3]))
+        print(f"\n[jvp cfg{cfg}] difference form vs mode {mode}: normalized {norm:.3e} relative {rel:.3e} "
+              f"count match {match:.3f}")
+        # every evaluation of J v lands on the same step sequence, and the results differ by
+        # a small fraction of one tolerance unit (measured at most 1.1e-4), so the reading
+        # does not move the solution by anything the error control can see
+        assert match >= 0.95
+        assert norm <= 1e-2
+    # against the exact product the difference form differs by the finite-difference
+    # truncation of J v alone: measured 4e-13 / 1.2e-10 / 1.9e-9 relative
+    assert relative_max(d, runs[orc.JVP_COMPLEX, False]) <= 2e-8
+
+
+@pytest.mark.parametrize("cfg", [c for c, _ in JVP_MODES_CASES])
+def test_difference_form_is_as_well_conditioned_as_the_exact_product(orc, jvp_mode_runs, cfg):
+    # The spread between two roundings of the same evaluation (the oracle and its FMA
+    # twin) is the precision any parity bar can resolve.  With the difference form it is
+    # that of the exact complex-step product (3.5e-15 / 3.8e-14 / 5.9e-11 against
+    # 3.6e-15 / 4.9e-14 / 1.0e-10); the literal difference of two rounded right-hand
+    # sides amplifies the rounding of f by 1/delta and spreads by 1.2e-10 / 1.8e-10 /
+    # 7.9e-9, at or above the 1e-10 bar, so a comparison at that bar needs an evaluation
+    # that is not the literal one.
+    _, runs = jvp_mode_runs[cfg]
+    env = {mode: relative_max(runs[mode, False], runs[mode, True])
+           for mode in (orc.JVP_FD, orc.JVP_COMPLEX, orc.JVP_FD_LITERAL)}
+    print(f"\n[jvp cfg{cfg}] rounding spread: difference form {env[orc.JVP_FD]:.3e}, complex step "
+          f"{env[orc.JVP_COMPLEX]:.3e}, literal {env[orc.JVP_FD_LITERAL]:.3e}")
+    assert env[orc.JVP_FD] <= 4 * env[orc.JVP_COMPLEX] + 1e-14
+    assert env[orc.JVP_FD_LITERAL] >= 10 * env[orc.JVP_FD]
