@@ -39,6 +39,7 @@ extern "C" {
 #define ROK4E_EHIP (-3)      /* HIP runtime or launch error */
 #define ROK4E_ECAPTURE (-4)  /* workspace too small, or PER_ATTEMPT, while the stream is being captured */
 #define ROK4E_ENOTSUP (-5)   /* no kernel variant for this (n_species, M, precision, layout) */
+#define ROK4E_ESTATIC (-6)   /* n_cells above ROK4E_STATIC_MAX_CELLS (rok4e_integrate_static) */
 
 /* Per-cell status codes. */
 #define ROK4E_CELL_OK 0
@@ -194,6 +195,31 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* mech, double* Y, double* T, 
  * Cells are handed out in array order; per-cell statistics as for rok4e_integrate. */
 int rok4e_integrate_conservative(int64_t n_cells, rok4e_mech* mech, double* U, const double* S,
                                  double* T_aux, double dt, double rtol, double atol, void* stream);
+
+/* Largest batch of rok4e_integrate_static: the size of its static device scratch. */
+#define ROK4E_STATIC_MAX_CELLS (1 << 21)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): rok4e_integrate_forced that calls no
+ * hipMalloc, hipFree or other allocating routine.  The same kernels and results (bit for
+ * bit, on the persistent schedule whatever the handle's scheduling option; the handle's
+ * method, M, precision, layout and cell order apply).  The per-call scratch (work-queue
+ * counter, queue-order bins and the order of up to ROK4E_STATIC_MAX_CELLS cells, 8 MiB)
+ * lives in a static device array of the library, one per GPU, held until the process
+ * ends; its address is looked up when a handle is first created on that GPU.  Every call
+ * on one GPU shares that array and keeps the last call's contents: calls that overlap on
+ * one GPU (two streams, two host threads, two handles) race and must be serialised by the
+ * caller.  The caller owns and passes the outputs: acc, rej, status (device int32
+ * [n_cells] each, required for n_cells > 0) receive each cell's accepted and rejected
+ * attempts and ROK4E_CELL_* status; rok4e_get_stats and the handle's per-cell arrays do
+ * not describe this call.  Y, T, p, S, dt, rtol, atol as for rok4e_integrate_forced (S may
+ * be NULL).  ROK4E_ESTATIC for n_cells > ROK4E_STATIC_MAX_CELLS; ROK4E_EINVAL for the
+ * argument errors of rok4e_integrate_forced or a missing output; n_cells == 0 is a
+ * no-op. */
+int rok4e_integrate_static(int64_t n_cells, rok4e_mech* mech, double* Y, double* T,
+                           const double* p, const double* S, double dt, double rtol,
+                           double atol, int32_t* acc, int32_t* rej, int32_t* status,
+                           void* stream);
 
 /* Launch tuning: integrates a copy of the given batch (Y, T, p as for rok4e_integrate;
  * the caller's arrays are not modified) once per waves-per-block choice 1..4 with the

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -343,6 +344,35 @@ static const Variant kVariants[] = {
 
 using namespace rok4e;
 
+// ----------------------------------------------------- static scratch ----
+// Device scratch of the allocation-free entry point rok4e_integrate_static, one copy per
+// GPU for the life of the process: word 0 the work-queue counter, words
+// [kScratchBins, kScratchBins + kOrderBins) the temperature-bin counters of the queue
+// order, and from kScratchOrder the queue order of up to ROK4E_STATIC_MAX_CELLS cells
+// (8 MiB in all).  Host code never passes the symbol itself to a kernel or a copy: the
+// device address of each GPU's copy comes from hipGetSymbolAddress (scratch_ptr).
+namespace rok4e {
+constexpr int kScratchBins = 64, kScratchOrder = 64 + kOrderBins;
+static __device__ __align__(256) unsigned int scratch[kScratchOrder + ROK4E_STATIC_MAX_CELLS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned int* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of scratch, looked up once per device
+// (the caller has made `device` current); null if the lookup fails.
+unsigned int* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[device] = (unsigned int*)ptr;
+  }
+  return g_scratch_ptr[device];
+}
+}  // namespace rok4e
+
 // ------------------------------------------------------------------- handle ----
 
 struct rok4e_mech {
@@ -366,6 +396,7 @@ struct rok4e_mech {
   DevMech cons_dm{};
   void* d_cons_image = nullptr;
   unsigned int* d_queue = nullptr;
+  unsigned int* scratch = nullptr;   // this device's static scratch (rok4e_integrate_static)
   // per-cell workspace
   int64_t cap = 0;
   int32_t* d_acc = nullptr;
@@ -611,15 +642,18 @@ int ensure_workspace(rok4e_mech* m, int64_t n, hipStream_t stream) {
 // captured launch replays them too.  Sets P.order.  Skipped for batches of fewer than
 // eight cells per segment in flight, where most cells start at once and the order
 // cannot shorten the tail by more than the kernels cost.
-void launch_order(rok4e_mech* m, const double* T, int64_t n, int64_t segments, hipStream_t st, Launch& P) {
+// bins (kOrderBins counters) and order (n entries) are device buffers: the handle's, or
+// the static scratch of rok4e_integrate_static.
+void launch_order(rok4e_mech* m, const double* T, int64_t n, int64_t segments, hipStream_t st, Launch& P,
+                  unsigned int* bins, int32_t* order) {
   P.order = nullptr;
   if (m->opt.cell_order != ROK4E_ORDER_HOT_FIRST || n < 8 * segments) return;
   const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)m->cu_count * 8);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, m->d_bins, kOrderBins, 0u);
-  hipLaunchKernelGGL(k_order_hist, dim3(grid), dim3(256), 0, st, T, n, m->d_bins);
-  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, st, m->d_bins);
-  hipLaunchKernelGGL(k_order_scatter, dim3(grid), dim3(256), 0, st, T, n, m->d_bins, m->d_order);
-  P.order = m->d_order;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, bins, kOrderBins, 0u);
+  hipLaunchKernelGGL(k_order_hist, dim3(grid), dim3(256), 0, st, T, n, bins);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, st, bins);
+  hipLaunchKernelGGL(k_order_scatter, dim3(grid), dim3(256), 0, st, T, n, bins, order);
+  P.order = order;
 }
 
 int check_state_args(int64_t n, rok4e_mech* mech, const void* Y, const void* T, const void* p) {
@@ -706,6 +740,7 @@ const char* rok4e_strerror(int code) {
     case ROK4E_EHIP: return "HIP runtime or launch error";
     case ROK4E_ECAPTURE: return "workspace too small during stream capture (call rok4e_reserve first)";
     case ROK4E_ENOTSUP: return "no kernel variant for this size, M, precision and layout";
+    case ROK4E_ESTATIC: return "batch larger than the static scratch of rok4e_integrate_static";
     default: return "unknown error";
   }
 }
@@ -780,6 +815,13 @@ int rok4e_mech_create(const rok4e_mech_desc* d, const rok4e_options* o, rok4e_me
   }
   m->cu_count = prop.multiProcessorCount;
   m->lds_per_block_max = prop.sharedMemPerBlock;
+  // the static scratch of this device: its address is looked up here, once per device,
+  // with the handle's device current
+  m->scratch = scratch_ptr(m->device);
+  if (!m->scratch) {
+    delete m;
+    return ROK4E_EHIP;
+  }
   hipError_t e = hipMalloc((void**)&m->d_queue, sizeof(unsigned int));
   if (e == hipSuccess) e = hipMemset(m->d_queue, 0, sizeof(unsigned int));
   int rc = e == hipSuccess ? ensure_image(m) : hip_fail(e);
@@ -849,7 +891,7 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
     if (m->opt.scheduling != ROK4E_PERSISTENT) return ROK4E_ENOTSUP;
     rc = shape_for(m, sl, n_cells, (const void*)m->var->rkdp, true, &sh);
     if (rc) return rc;
-    launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P);
+    launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P, m->d_bins, m->d_order);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
     hipLaunchKernelGGL(m->var->rkdp, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
     const hipError_t e = hipGetLastError();
@@ -870,7 +912,7 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
   }
   rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate, true, &sh);
   if (rc) return rc;
-  launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P);
+  launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P, m->d_bins, m->d_order);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
   hipLaunchKernelGGL(m->var->integrate, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
   const hipError_t e = hipGetLastError();
@@ -935,6 +977,43 @@ int rok4e_integrate_forced(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
 int rok4e_integrate(int64_t n_cells, rok4e_mech* m, double* Y, double* T, const double* p, double dt,
                     double rtol, double atol, void* stream) {
   return rok4e_integrate_ex(n_cells, m, Y, T, p, nullptr, nullptr, dt, rtol, atol, stream);
+}
+
+int rok4e_integrate_static(int64_t n_cells, rok4e_mech* m, double* Y, double* T, const double* p,
+                           const double* S, double dt, double rtol, double atol, int32_t* acc,
+                           int32_t* rej, int32_t* status, void* stream) {
+  int rc = check_state_args(n_cells, m, Y, T, p);
+  if (rc) return rc;
+  if (n_cells > 0 && (!acc || !rej || !status)) return ROK4E_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(rtol > 0.0) || !(atol >= 0.0) || !std::isfinite(rtol) ||
+      !std::isfinite(atol))
+    return ROK4E_EINVAL;
+  if (n_cells > ROK4E_STATIC_MAX_CELLS) return ROK4E_ESTATIC;
+  if (n_cells == 0) return ROK4E_OK;
+  if (!m->scratch) return ROK4E_EHIP;
+  hipStream_t st = (hipStream_t)stream;
+  const SegLayout sl = seg_layout(m->nr, *m->var);
+  Launch P = base_launch(m, n_cells, Y, T, p, S, sl);
+  P.dt = dt;
+  P.rtol = rtol;
+  P.atol = atol;
+  P.queue = m->scratch;
+  P.acc = acc;
+  P.rej = rej;
+  P.status = status;
+  const bool rkdp = m->opt.method == ROK4E_METHOD_RKDP45;
+  const IntegrateFn kern = rkdp ? m->var->rkdp : m->var->integrate;
+  LaunchShape sh;
+  rc = shape_for(m, sl, n_cells, (const void*)kern, true, &sh);
+  if (rc) return rc;
+  launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P, m->scratch + kScratchBins,
+               (int32_t*)(m->scratch + kScratchOrder));
+  // the queue counter starts at zero: a one-thread kernel clears it (no memset node)
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->scratch);
+  hipLaunchKernelGGL(kern, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e);
+  return ROK4E_OK;
 }
 
 int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T, const double* p,

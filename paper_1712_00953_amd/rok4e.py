@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # tuning macros); by default the in-tree build is loaded.
 LIB_PATH = os.environ.get("ROK4E_LIB") or os.path.join(HERE, "librok4e.so")
 
-OK, EINVAL, ENOMEM, EHIP, ECAPTURE, ENOTSUP = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, ECAPTURE, ENOTSUP, ESTATIC = 0, -1, -2, -3, -4, -5, -6
+STATIC_MAX_CELLS = 1 << 21
 FP64, MIXED = 0, 1
 PERSISTENT, PER_ATTEMPT = 0, 1
 SPLIT_SIMPLER, SPLIT_STRANG = 0, 1
@@ -27,7 +28,7 @@ CELL_OK, CELL_MAX_ATTEMPTS, CELL_STEP_UNDERFLOW, CELL_BAD_INPUT = 0, 1, 2, 3
 
 EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "rok4e_set_options",
            "rok4e_get_options", "rok4e_reserve", "rok4e_integrate", "rok4e_integrate_forced",
-           "rok4e_integrate_ex", "rok4e_integrate_conservative",
+           "rok4e_integrate_ex", "rok4e_integrate_conservative", "rok4e_integrate_static",
            "rok4e_tune", "rok4e_rhs", "rok4e_arnoldi", "rok4e_transport", "rok4e_split_workspace_bytes",
            "rok4e_split_step", "rok4e_get_stats", "rok4e_cell_stats_ptr",
            "rok4e_copy_cell_stats", "rok4e_strerror"]
@@ -90,6 +91,7 @@ def load():
         lib.rok4e_integrate_forced.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_ex.argtypes = [i64, vp, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_conservative.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, vp]
+        lib.rok4e_integrate_static.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp]
         lib.rok4e_tune.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_float), vp]
         lib.rok4e_rhs.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
@@ -236,6 +238,24 @@ class Mech:
                                        float(rtol), float(atol), _stream(stream))
         _check(rc, "rok4e_integrate")
         self.n_last = n
+
+    def integrate_static(self, Y, T, p, dt, rtol, atol, acc, rej, status, S=None, stream=None,
+                         n_cells=None):
+        """rok4e_integrate_static: as integrate (forcing S optional), allocating nothing;
+        the per-cell accepted / rejected counts and status go to the int32 device tensors
+        acc, rej, status [n]."""
+        n = int(T.shape[0]) if n_cells is None else int(n_cells)
+        ns = self.n_species
+        for t, rows, name in ((Y, ns, "Y"), (T, 1, "T"), (p, 1, "p"), (S, ns + 1, "S")):
+            _need(t, rows * n, name, rows=rows)
+        for t, name in ((acc, "acc"), (rej, "rej"), (status, "status")):
+            if n > 0 and t is None:
+                raise ValueError(f"{name}: required")
+            _need(t, n, name, "int32", rows=1)
+        rc = load().rok4e_integrate_static(n, self._h, _ptr(Y), _ptr(T), _ptr(p), _ptr(S), float(dt),
+                                           float(rtol), float(atol), _ptr(acc), _ptr(rej), _ptr(status),
+                                           _stream(stream))
+        _check(rc, "rok4e_integrate_static")
 
     def integrate_conservative(self, U, dt, rtol, atol, S=None, T_aux=None, stream=None, n_cells=None):
         """In-place reaction substep of the conservative variables U [(ns+5), n] (float64
