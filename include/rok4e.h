@@ -104,7 +104,8 @@ typedef struct {
   int32_t fixed_steps;    /* 0: adaptive; n > 0: n equal steps, no error control */
   int32_t lanes_per_cell; /* 0: automatic; else 16, 32 or 64.  Changes the order in which
                              the production sums accumulate: results agree to rounding */
-  int32_t waves_per_block;/* 0: automatic; 1..4 waves of 64 lanes (bitwise neutral) */
+  int32_t waves_per_block;/* 0: automatic; 1..8 waves of 64 lanes per block (bitwise neutral;
+                             layouts of one row slot per lane take at most 4) */
   int32_t blocks_per_cu;  /* 0: automatic; persistent-grid blocks per compute unit
                              (bitwise neutral) */
   int32_t scheduling;     /* ROK4E_PERSISTENT or ROK4E_PER_ATTEMPT (bitwise neutral) */

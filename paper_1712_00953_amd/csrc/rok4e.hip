@@ -78,42 +78,102 @@ __global__ void __launch_bounds__(256) k_order_scatter(const double* T, int64_t 
 #endif
 template <int ROWS>
 constexpr int occupancy() { return ROWS == 1 ? ROK4E_OCC_ROWS1 : 2; }
+// Largest block of the persistent integrator: four waves for one row slot per lane, eight
+// for larger layouts (eight waves over the four SIMDs at two waves per SIMD: one block,
+// one copy of the mechanism tables in LDS, fills a compute unit).
+template <int ROWS>
+constexpr int integrate_max_threads() { return ROWS == 1 ? 256 : 512; }
 
 // FORM selects the state: the 0-D reactor (Y, T; p per cell) or the conservative
 // variables with the auxiliary temperature (P.Y = U, P.T = the final temperatures or
-// null; FP64; array order, no carried steps).
+// null; FP64; no carried steps).
+//
+// With one segment per wave, each cell is integrated to the end before the next is
+// taken.  With several segments per wave, one loop over attempts: on every pass each
+// segment makes one attempt on its cell, and a segment whose cell is done first stores it
+// and takes the next cell from the queue, so the segments stay in step attempt by attempt
+// instead of the wave waiting for its slowest cell before any segment takes a new one; the
+// wave leaves the loop when none of its segments holds a cell.
 template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor>
-__global__ void __launch_bounds__(256, occupancy<ROWS>()) k_integrate(DevMech m, Launch P) {
+__global__ void __launch_bounds__(integrate_max_threads<ROWS>(), occupancy<ROWS>())
+    k_integrate(DevMech m, Launch P) {
   extern __shared__ __align__(16) char smem[];
   const MechLds t = load_mech_lds<L>(m, smem);
   const int lane = (int)(threadIdx.x % L);
   char* seg = smem + m.image_bytes + (threadIdx.x / L) * P.seg_bytes;
   const SegLds<RT> S = seg_lds<RT>(seg, P);
   init_seg<RT>(m, S);
-  while (true) {
-    // Every lane takes part in the atomic (the segment's first lane adds 1, the others
-    // 0), so no lane-dependent branch surrounds the value that is then broadcast.
-    const unsigned int ticket = atomicAdd(P.queue, lane == 0 ? 1u : 0u);
-    const int tk = seg_bcast<L>((int)ticket, 0);
-    if (tk < 0 || (int64_t)tk >= P.n_cells) break;
-    const int cell = P.order ? P.order[tk] : tk;
-    double u[ROWS], s[ROWS], p = 0.0;
-    CellState c{};
-    c.status = 3;
-    if constexpr (FORM == kFormConservative) {
-      if (load_cell_cons<L, ROWS>(m, t, P, cell, lane, u, s)) {
-        c = integrate_cell<L, ROWS, MMAX, RT, FORM>(m, t, P, u, p, s, S, lane);
-        store_cell_cons<L, ROWS>(m, P, cell, lane, u);
+  if constexpr (L == 64) {
+    // one segment per wave: each cell integrated to the end before the next is taken
+    while (true) {
+      const unsigned int ticket = atomicAdd(P.queue, lane == 0 ? 1u : 0u);
+      const int tk = seg_bcast<L>((int)ticket, 0);
+      if (tk < 0 || (int64_t)tk >= P.n_cells) break;
+      const int cell = P.order ? P.order[tk] : tk;
+      double u[ROWS], s[ROWS], p = 0.0;
+      CellState c{};
+      c.status = 3;
+      if constexpr (FORM == kFormConservative) {
+        if (load_cell_cons<L, ROWS>(m, t, P, cell, lane, u, s)) {
+          c = integrate_cell<L, ROWS, MMAX, RT, FORM>(m, t, P, u, p, s, S, lane);
+          store_cell_cons<L, ROWS>(m, P, cell, lane, u);
+        }
+      } else if (load_cell<L, ROWS>(m, P, cell, lane, u, s, p)) {
+        c = integrate_cell<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane, P.hio ? P.hio[cell] : 0.0);
+        store_cell<L, ROWS>(m, P, cell, lane, u);
+        if (P.hio) P.hio[cell] = c.hnext;
       }
-    } else if (load_cell<L, ROWS>(m, P, cell, lane, u, s, p)) {
-      c = integrate_cell<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane, P.hio ? P.hio[cell] : 0.0);
-      store_cell<L, ROWS>(m, P, cell, lane, u);
-      if (P.hio) P.hio[cell] = c.hnext;
+      P.acc[cell] = c.accepted;
+      P.rej[cell] = c.rejected;
+      P.status[cell] = c.status;
     }
-    // every lane of the segment stores the same (segment-uniform) values
-    P.acc[cell] = c.accepted;
-    P.rej[cell] = c.rejected;
-    P.status[cell] = c.status;
+    return;
+  }
+  double u[ROWS], s[ROWS], fn[ROWS], Q[ROWS][MMAX];
+  double p = 0.0;
+  CellState c{};
+  int cell = -1;          // the segment's cell (segment-uniform), -1 for none
+  bool drained = false;   // the queue has run out for this segment
+  while (true) {
+    if (cell >= 0 && !cell_running(P, c)) {
+      if constexpr (FORM == kFormConservative) {
+        store_cell_cons<L, ROWS>(m, P, cell, lane, u);
+      } else {
+        store_cell<L, ROWS>(m, P, cell, lane, u);
+        if (P.hio) P.hio[cell] = c.hnext;
+      }
+      // every lane of the segment stores the same (segment-uniform) values
+      P.acc[cell] = c.accepted;
+      P.rej[cell] = c.rejected;
+      P.status[cell] = c.status;
+      cell = -1;
+    }
+    while (cell < 0 && !drained) {
+      // Every lane takes part in the atomic (the segment's first lane adds 1, the others
+      // 0), so no lane-dependent branch surrounds the value that is then broadcast.
+      const unsigned int ticket = atomicAdd(P.queue, lane == 0 ? 1u : 0u);
+      const int tk = seg_bcast<L>((int)ticket, 0);
+      if (tk < 0 || (int64_t)tk >= P.n_cells) {
+        drained = true;
+        break;
+      }
+      const int cand = P.order ? P.order[tk] : tk;
+      bool ok;
+      if constexpr (FORM == kFormConservative) ok = load_cell_cons<L, ROWS>(m, t, P, cand, lane, u, s);
+      else ok = load_cell<L, ROWS>(m, P, cand, lane, u, s, p);
+      if (ok) {
+        cell = cand;
+        // a new cell always needs an attempt (t = 0 < dt, no attempt made yet)
+        cell_start(P, c, (FORM == kFormReactor && P.hio) ? P.hio[cand] : 0.0);
+      } else {
+        // invalid input: the state is left as it is
+        P.acc[cand] = 0;
+        P.rej[cand] = 0;
+        P.status[cand] = 3;
+      }
+    }
+    if (!__any(cell >= 0)) break;
+    if (cell >= 0) cell_attempt<L, ROWS, MMAX, RT, FORM>(m, t, P, u, p, s, S, lane, c, fn, Q);
   }
 }
 
@@ -340,6 +400,9 @@ static const Variant kVariants[] = {
     ROK4E_VARIANT(64, 2, 16, float, ROK4E_MIXED),
 };
 
+// Largest block of a variant's persistent integrator, in waves.
+inline int integrate_waves(const Variant& v) { return v.rows == 1 ? 4 : 8; }
+
 }  // namespace rok4e
 
 using namespace rok4e;
@@ -426,7 +489,7 @@ bool options_ok(const rok4e_options& o) {
   if (o.fixed_steps < 0) return false;
   if (o.lanes_per_cell != 0 && o.lanes_per_cell != 16 && o.lanes_per_cell != 32 && o.lanes_per_cell != 64)
     return false;
-  if (o.waves_per_block < 0 || o.waves_per_block > 4) return false;
+  if (o.waves_per_block < 0 || o.waves_per_block > 8) return false;
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return false;
   if (o.scheduling != ROK4E_PERSISTENT && o.scheduling != ROK4E_PER_ATTEMPT) return false;
   if (o.method != ROK4E_METHOD_ROK4E && o.method != ROK4E_METHOD_RKDP45) return false;
@@ -573,11 +636,13 @@ struct LaunchShape {
 // Launch shape: blocks of `waves_per_block` waves (fewer if the block's LDS would not
 // fit), as many blocks per CU as occupancy allows for a persistent launch, never more
 // segments than cells.
+// max_wpb: the kernel's largest block in waves (its launch bounds).
 int shape_for(const rok4e_mech* m, const SegLayout& sl, int64_t n_cells, const void* kernel,
-              bool persistent, LaunchShape* out, const Variant* var = nullptr, const DevMech* dmp = nullptr) {
+              bool persistent, LaunchShape* out, const Variant* var = nullptr, const DevMech* dmp = nullptr,
+              int max_wpb = 4) {
   const Variant& v = var ? *var : *m->var;
   const DevMech& dm = dmp ? *dmp : m->dm;
-  int wpb = m->opt.waves_per_block > 0 ? m->opt.waves_per_block : 4;
+  int wpb = std::min(m->opt.waves_per_block > 0 ? m->opt.waves_per_block : max_wpb, max_wpb);
   const int segs_per_wave = 64 / v.L;
   while (wpb > 1 && (size_t)(dm.image_bytes + wpb * segs_per_wave * sl.bytes) > m->lds_per_block_max) --wpb;
   LaunchShape s{};
@@ -910,7 +975,8 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
     m->last_n = n_cells;
     return ROK4E_OK;
   }
-  rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate, true, &sh);
+  rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate, true, &sh, nullptr, nullptr,
+                 integrate_waves(*m->var));
   if (rc) return rc;
   launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P, m->d_bins, m->d_order);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
@@ -959,7 +1025,7 @@ int rok4e_integrate_conservative(int64_t n_cells, rok4e_mech* m, double* U, cons
   P.rtol = rtol;
   P.atol = atol;
   LaunchShape sh;
-  rc = shape_for(m, sl, n_cells, (const void*)var->integrate_cons, true, &sh, var, dm);
+  rc = shape_for(m, sl, n_cells, (const void*)var->integrate_cons, true, &sh, var, dm, integrate_waves(*var));
   if (rc) return rc;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
   hipLaunchKernelGGL(var->integrate_cons, dim3(sh.grid), dim3(sh.block), sh.lds, st, *dm, P);
@@ -1004,7 +1070,7 @@ int rok4e_integrate_static(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
   const bool rkdp = m->opt.method == ROK4E_METHOD_RKDP45;
   const IntegrateFn kern = rkdp ? m->var->rkdp : m->var->integrate;
   LaunchShape sh;
-  rc = shape_for(m, sl, n_cells, (const void*)kern, true, &sh);
+  rc = shape_for(m, sl, n_cells, (const void*)kern, true, &sh, nullptr, nullptr, rkdp ? 4 : integrate_waves(*m->var));
   if (rc) return rc;
   launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P, m->scratch + kScratchBins,
                (int32_t*)(m->scratch + kScratchOrder));

@@ -155,43 +155,6 @@ __device__ __forceinline__ float readlane(float x, int l) {
 }
 __device__ __forceinline__ int readlane(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
 
-// Sum over the L lanes of a segment; every lane receives the result.  Within a row of 16
-// lanes a butterfly of DPP moves leaves the row sum in every lane; across rows the sums
-// are combined pairwise with row broadcasts ((r0 + r1) + (r2 + r3) for a full wave), all
-// on the vector ALU.  Additions are commutative bit for bit, so every lane, and every
-// layout, gets the same bits.
-template <int L, class V>
-__device__ __forceinline__ V seg_sum1(V x) {
-  x = x + dpp<0xB1>(x);     // quad_perm [1,0,3,2]
-  x = x + dpp<0x4E>(x);     // quad_perm [2,3,0,1]
-  x = x + dpp<0x141>(x);    // row_half_mirror: pairs the two quads of each half-row
-  x = x + dpp<0x140>(x);    // row_mirror: pairs the two half-rows of each row
-  if constexpr (L >= 32) {
-    x = x + dpp_rows<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3: r0 + r1, r2 + r3
-  }
-  if constexpr (L == 64) {
-    x = x + dpp_rows<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
-    x = readlane(x, 63);
-  } else if constexpr (L == 32) {
-    const V a = readlane(x, 31), b = readlane(x, 63);
-    x = (threadIdx.x & 32) ? b : a;
-  }
-  return x;
-}
-
-// Sum over all rows of a segment: per-slot lane reduction, then slots pairwise.
-template <int L, int ROWS, class V>
-__device__ __forceinline__ V seg_sum(const V (&x)[ROWS]) {
-  if constexpr (ROWS == 1) {
-    return seg_sum1<L>(x[0]);
-  } else if constexpr (ROWS == 2) {
-    return seg_sum1<L>(x[0]) + seg_sum1<L>(x[1]);
-  } else {
-    static_assert(ROWS == 4, "ROWS must be 1, 2 or 4");
-    return (seg_sum1<L>(x[0]) + seg_sum1<L>(x[1])) + (seg_sum1<L>(x[2]) + seg_sum1<L>(x[3]));
-  }
-}
-
 // x + (x of lane i ^ 16) and x + (x of lane i ^ 32) in every lane, from the gfx950
 // row-swap permutes (v_permlane16_swap / v_permlane32_swap of x with itself leave the two
 // partners' values in two registers; their sum has the same bits in both lanes).
@@ -216,60 +179,138 @@ __device__ __forceinline__ float add_xor32(float x) {
   return __uint_as_float(v[0]) + __uint_as_float(v[1]);
 }
 
+// Split exchange of two values a, b across lane ^ 32 (D = 32) or lane ^ 16 (D = 16): one
+// row-swap permute per 32-bit word moves the b of the lower partner and the a of the upper
+// one across, so that the sum is a + a' in the lanes whose bit log2(D) is clear and
+// b + b' in the others: two reductions advance one level for the cost of one.
+template <int D>
+__device__ __forceinline__ double swap_split(double a, double b) {
+  const unsigned alo = (unsigned)__double2loint(a), ahi = (unsigned)__double2hiint(a);
+  const unsigned blo = (unsigned)__double2loint(b), bhi = (unsigned)__double2hiint(b);
+  if constexpr (D == 32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+  }
+}
+template <int D>
+__device__ __forceinline__ float swap_split(float a, float b) {
+  if constexpr (D == 32) {
+    const auto v = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(v[0]) + __uint_as_float(v[1]);
+  } else {
+    const auto v = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(v[0]) + __uint_as_float(v[1]);
+  }
+}
+
+// The levels of a segment reduction, each pairing every lane with the lane whose index
+// differs by an XOR mask: lane ^ 32 and lane ^ 16 (row-swap permutes), then within a
+// 16-lane row lane ^ 15 (row mirror), lane ^ 7 (half-row mirror), lane ^ 2 and lane ^ 1
+// (quad permutes).  The masks span the lane index bits, so after all levels from the
+// segment's first one every lane holds the segment sum; every level is symmetric and
+// additions commute bit for bit, so every lane holds the same bits.
+//   level 0: ^32, 1: ^16, 2: ^15, 3: ^7, 4: ^2, 5: ^1
+// When a level splits a pair of values, the lanes keep the value selected by the level's
+// bit (32: bit 5, 16: bit 4, 15: bit 3, 7: bit 2, 2: bit 1, 1: bit 0).
+constexpr int kLevelBit[6] = {5, 4, 3, 2, 1, 0};
+template <int LEVEL>
+constexpr int level_dpp() { return LEVEL == 2 ? 0x140 : LEVEL == 3 ? 0x141 : LEVEL == 4 ? 0x4E : 0xB1; }
+
+template <int LEVEL, class V>
+__device__ __forceinline__ V level_full(V x) {
+  if constexpr (LEVEL == 0) return add_xor32(x);
+  else if constexpr (LEVEL == 1) return add_xor16(x);
+  else return x + dpp<level_dpp<LEVEL>()>(x);
+}
+
+template <int LEVEL, class V>
+__device__ __forceinline__ V level_split(V a, V b, int lid) {
+  if constexpr (LEVEL == 0) return swap_split<32>(a, b);
+  else if constexpr (LEVEL == 1) return swap_split<16>(a, b);
+  else {
+    const bool hi = ((lid >> kLevelBit[LEVEL]) & 1) != 0;
+    const V keep = hi ? b : a, send = hi ? a : b;
+    return keep + dpp<level_dpp<LEVEL>()>(send);
+  }
+}
+
+// Levels LEVEL..5 applied to NV values (NV a power of two): the first log2(NV) levels
+// split pairs, the rest sum fully.  On return each lane holds one partial: the sum of value
+// i, i = sum over the splitting levels j of (lane bit of level j) << j, over the segment.
+template <int LEVEL, int NV, class V>
+__device__ __forceinline__ V seg_levels(const V (&v)[NV], int lid) {
+  if constexpr (LEVEL == 6) {
+    static_assert(NV == 1, "more values than split levels");
+    return v[0];
+  } else if constexpr (NV == 1) {
+    V w[1] = {level_full<LEVEL>(v[0])};
+    return seg_levels<LEVEL + 1, 1>(w, lid);
+  } else {
+    V w[NV / 2];
+#pragma unroll
+    for (int m = 0; m < NV / 2; ++m) w[m] = level_split<LEVEL>(v[2 * m], v[2 * m + 1], lid);
+    return seg_levels<LEVEL + 1, NV / 2>(w, lid);
+  }
+}
+
+template <int L>
+constexpr int first_level() { return L == 64 ? 0 : (L == 32 ? 1 : 2); }
+
+// Lane (within the segment) that holds the sum of value i after seg_levels from the
+// segment's first level.
+template <int L>
+__device__ __forceinline__ constexpr int sum_lane(int i) {
+  int lane = 0;
+  for (int j = 0; (1 << j) <= i; ++j)
+    if ((i >> j) & 1) lane |= 1 << kLevelBit[first_level<L>() + j];
+  return lane;
+}
+
+// Sum over the L lanes of a segment; every lane receives the result (the same bits in
+// every lane of the segment).
+template <int L, class V>
+__device__ __forceinline__ V seg_sum1(V x) {
+  V v[1] = {x};
+  return seg_levels<first_level<L>(), 1>(v, 0);
+}
+
+// Sum over all rows of a segment: the slots added in each lane, then one lane reduction.
+template <int L, int ROWS, class V>
+__device__ __forceinline__ V seg_sum(const V (&x)[ROWS]) {
+  if constexpr (ROWS == 1) {
+    return seg_sum1<L>(x[0]);
+  } else if constexpr (ROWS == 2) {
+    return seg_sum1<L>(x[0] + x[1]);
+  } else {
+    static_assert(ROWS == 4, "ROWS must be 1, 2 or 4");
+    return seg_sum1<L>((x[0] + x[1]) + (x[2] + x[3]));
+  }
+}
+
 // Sums over the L lanes of a segment of K values at once (K = 2, 4 or 8); every lane
-// receives all K sums in x.  On the first log2(min(K, 4)) butterfly levels (lane ^ 1,
-// lane ^ 2) the values are split between partner lanes: of every pair of values a lane
-// keeps one, chosen by its lane-index bit, and sends the other, so a level costs half the
-// moves and adds of K separate reductions.  The kept values are then summed over the
-// lanes with the same two low index bits: within a row by rotations by 4 and 8, across
-// rows by the lane ^ 16 and lane ^ 32 swaps.  Sum i is read from one fixed lane of the
-// segment (the rotation sums differ by lane in summation order, so the result is taken
-// from the same lane every time).
+// receives all K sums in x.  The first log2(K) levels split the values between partner
+// lanes (a level costs one exchange and one add for two sums), the remaining levels sum
+// the one partial left; sum i is then read from the lane that holds it.
 template <int L, int K, class V>
 __device__ __forceinline__ void seg_sum_k(V (&x)[K]) {
   static_assert(K == 2 || K == 4 || K == 8, "K must be 2, 4 or 8");
   const int lid = (int)(threadIdx.x & 63);
-  const bool b0 = lid & 1, b1 = lid & 2;
-  constexpr int K1 = K / 2;
-  V y[K1];
-#pragma unroll
-  for (int m = 0; m < K1; ++m) {
-    const V keep = b0 ? x[2 * m + 1] : x[2 * m], send = b0 ? x[2 * m] : x[2 * m + 1];
-    y[m] = keep + dpp<0xB1>(send);            // quad_perm [1,0,3,2]: lane ^ 1
-  }
-  constexpr int K2 = K1 > 1 ? K1 / 2 : 1;
-  V z[K2];
-  if constexpr (K1 > 1) {
-#pragma unroll
-    for (int n = 0; n < K2; ++n) {
-      const V keep = b1 ? y[2 * n + 1] : y[2 * n], send = b1 ? y[2 * n] : y[2 * n + 1];
-      z[n] = keep + dpp<0x4E>(send);          // quad_perm [2,3,0,1]: lane ^ 2
-    }
-  } else {
-    z[0] = y[0] + dpp<0x4E>(y[0]);
-  }
-#pragma unroll
-  for (int n = 0; n < K2; ++n) {
-    V v = z[n];
-    v = v + dpp<0x124>(v);                     // row_ror:4
-    v = v + dpp<0x128>(v);                     // row_ror:8
-    if constexpr (L >= 32) v = add_xor16(v);
-    if constexpr (L == 64) v = add_xor32(v);
-    z[n] = v;
-  }
-  // Sum i sits in the lanes whose two low index bits are (i & 3) for K >= 4, (i & 1)
-  // with K = 2; it is read from the first such lane of the segment.
+  const V z = seg_levels<first_level<L>(), K>(x, lid);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    const int n = K >= 4 ? i >> 2 : 0;
-    const int q = K >= 4 ? (i & 3) : (i & 1);
+    const int q = sum_lane<L>(i);
     if constexpr (L == 64) {
-      x[i] = readlane(z[n], q);
+      x[i] = readlane(z, q);
     } else if constexpr (L == 32) {
-      const V a = readlane(z[n], q), c = readlane(z[n], 32 + q);
+      const V a = readlane(z, q), c = readlane(z, 32 + q);
       x[i] = (lid & 32) ? c : a;
     } else {
-      x[i] = __shfl(z[n], (lid & ~15) + q, 64);
+      x[i] = __shfl(z, (lid & ~15) + q, 64);
     }
   }
 }
