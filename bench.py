@@ -87,7 +87,9 @@ def timed_events(torch, stream, fn, reps):
     return [a.elapsed_time(b) * 1e-3 for a, b in ev]
 
 
-def run_gpu(w, precision, steps, warmup, R, torch):
+def run_gpu(w, precision, steps, warmup, R, torch, tune=True):
+    """The timed integration of the batch.  With tune, the launch tuner first picks the
+    launch layout on a copy of the same batch (outside the timed region)."""
     from paper_1712_00953_amd import workmodel
     st = w.states
     n = st.n_cells
@@ -99,6 +101,7 @@ def run_gpu(w, precision, steps, warmup, R, torch):
     copies = [(Y0.clone(), T0.clone()) for _ in range(warmup + steps)]
     m = R.Mech(w.mech, M=w.M, precision=precision, max_attempts=200000)
     m.reserve(n)
+    tuning = m.tune(Y0, T0, p, w.dt, w.rtol, w.atol) if tune else None
     stream = torch.cuda.current_stream()   # the stream the library launches on
     for i in range(warmup):
         m.integrate(copies[i][0], copies[i][1], p, w.dt, w.rtol, w.atol)
@@ -114,6 +117,9 @@ def run_gpu(w, precision, steps, warmup, R, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = [a.elapsed_time(b) for a, b in ev]
+    o = m.get_options()
+    layout = {"lanes_per_cell": o.lanes_per_cell, "waves_per_block": o.waves_per_block,
+              "jvp_gather": ["auto", "lds", "private"][o.jvp_gather]}
     stats = m.stats()
     acc = torch.zeros(n, dtype=torch.int32)
     rej = torch.zeros(n, dtype=torch.int32)
@@ -137,7 +143,8 @@ def run_gpu(w, precision, steps, warmup, R, torch):
                 attempts_per_cell={q: int(np.percentile(S, float(q[1:]))) for q in ("p50", "p90", "p99")}
                 | {"min": int(S.min()), "max": int(S.max()), "mean": float(S.mean())},
                 attempts_per_s=(stats["accepted"] + stats["rejected"]) / kavg,
-                final_state=(Yl, Tl), cell_counts=(acc.numpy(), rej.numpy()))
+                final_state=(Yl, Tl), cell_counts=(acc.numpy(), rej.numpy()), layout=layout,
+                tuning=tuning)
 
 
 def run_subsystems(w, R, torch, reps=5):
@@ -180,9 +187,11 @@ def run_schedules(R, torch, synth):
     T0 = torch.tensor(st.T, dtype=torch.float64, device=dev)
     p = torch.tensor(st.p, dtype=torch.float64, device=dev)
     out, res = {}, {}
-    for name, sched in (("persistent", R.PERSISTENT), ("per_attempt", R.PER_ATTEMPT)):
+    for name, sched, tune in (("persistent", R.PERSISTENT, False), ("persistent_tuned", R.PERSISTENT, True),
+                              ("per_attempt", R.PER_ATTEMPT, False)):
         m = R.Mech(w.mech, M=w.M, max_attempts=200000, scheduling=sched)
         m.reserve(n)
+        tuning = m.tune(Y0, T0, p, w.dt, w.rtol, w.atol, force=True) if tune else None
         Y, T = Y0.clone(), T0.clone()
         m.integrate(Y, T, p, w.dt, w.rtol, w.atol)
         Y.copy_(Y0)
@@ -195,9 +204,14 @@ def run_schedules(R, torch, synth):
         s = m.stats()
         m.close()
         res[name] = (Y, T)
+        o = m.get_options()
         out[name] = {"cells_per_s": n / el, "ms": el * 1e3, "attempts": s["accepted"] + s["rejected"],
-                     "max_attempts_cell": s["max_attempts"]}
+                     "max_attempts_cell": s["max_attempts"], "lanes_per_cell": o.lanes_per_cell,
+                     "waves_per_block": o.waves_per_block, "jvp_gather": o.jvp_gather}
+        if tuning is not None:
+            out[name]["tuning"] = tuning
     out["speedup_persistent"] = out["persistent"]["cells_per_s"] / out["per_attempt"]["cells_per_s"]
+    out["speedup_tuned_vs_default"] = out["persistent_tuned"]["cells_per_s"] / out["persistent"]["cells_per_s"]
     out["bitwise_equal"] = bool(torch.equal(res["persistent"][0], res["per_attempt"][0])
                                 and torch.equal(res["persistent"][1], res["per_attempt"][1]))
     out["workload"] = w.name + " (pre-exponential factors x 1e-8)"
@@ -551,6 +565,8 @@ def main():
                    "attempts_per_step": fp64["attempts"], "max_attempts_cell": fp64["max_attempts"]},
         "attempts": {"per_cell": fp64["attempts_per_cell"], "per_s": fp64["attempts_per_s"],
                      "accepted": fp64["accepted"], "rejected": fp64["rejected"]},
+        "layout": fp64["layout"],
+        "tuning": fp64["tuning"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
@@ -582,7 +598,8 @@ def main():
         out["mixed"] = {"value": mixed["cells_per_s"], "unit": "cell-integrations/s",
                         "ms_per_step": mixed["ms_per_step"], "dtype": "f32 rates / f64 state",
                         "speedup_vs_fp64": mixed["cells_per_s"] / fp64["cells_per_s"],
-                        "attempts_per_step": mixed["attempts"],
+                        "attempts_per_step": mixed["attempts"], "layout": mixed["layout"],
+                        "tuning": mixed["tuning"],
                         "tflops_fp64_equivalent": mixed["tflops"],
                         "max_rel_err_vs_fp64": float(max(relY.max(), relT.max())),
                         "p99_rel_err_vs_fp64": float(np.percentile(relY, 99)),

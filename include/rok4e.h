@@ -78,6 +78,15 @@ extern "C" {
 #define ROK4E_ORDER_HOT_FIRST 0
 #define ROK4E_ORDER_ARRAY 1
 
+/* Where the Jacobian-vector products of the Arnoldi process (Sec. 4.3) read the base-state
+ * concentrations of each lane's reactions (bitwise neutral: the same values either way).
+ * LDS: from the segment's LDS arrays.  PRIVATE: from a copy gathered into lane-private
+ * memory once per basis (64-lane, one-slot layouts with M <= 8 only; elsewhere LDS).
+ * AUTO: LDS, unless rok4e_tune chose otherwise. */
+#define ROK4E_GATHER_AUTO 0
+#define ROK4E_GATHER_LDS 1
+#define ROK4E_GATHER_PRIVATE 2
+
 typedef struct rok4e_mech rok4e_mech;   /* opaque handle */
 
 /* Mechanism description; host arrays, copied to the device by rok4e_mech_create. */
@@ -112,8 +121,22 @@ typedef struct {
   int32_t method;         /* ROK4E_METHOD_ROK4E (default) or ROK4E_METHOD_RKDP45 */
   int32_t cell_order;     /* ROK4E_ORDER_HOT_FIRST (default) or ROK4E_ORDER_ARRAY (bitwise
                              neutral; persistent schedule) */
+  int32_t jvp_gather;     /* ROK4E_GATHER_AUTO (default), _LDS or _PRIVATE (bitwise neutral;
+                             persistent schedule) */
   double h0;              /* first trial step; <= 0 means dt */
 } rok4e_options;
+
+/* Outcome of rok4e_tune. */
+typedef struct {
+  int32_t lanes_per_cell;  /* the chosen launch layout, also written to the handle's options */
+  int32_t waves_per_block;
+  int32_t blocks_per_cu;
+  int32_t jvp_gather;
+  float ms;                /* time of one integration of the batch with the choice */
+  float ms_default;        /* the same with the options the handle had before (0 on a cache hit) */
+  int32_t candidates;      /* layouts timed (0 on a cache hit) */
+  int32_t from_cache;      /* 1: the choice came from the tuning cache and nothing was timed */
+} rok4e_tune_result;
 
 typedef struct {
   int64_t n_cells;        /* cells of the last integrate call */
@@ -222,15 +245,24 @@ int rok4e_integrate_static(int64_t n_cells, rok4e_mech* mech, double* Y, double*
                            double atol, int32_t* acc, int32_t* rej, int32_t* status,
                            void* stream);
 
-/* Launch tuning: integrates a copy of the given batch (Y, T, p as for rok4e_integrate;
- * the caller's arrays are not modified) once per waves-per-block choice 1..4 with the
- * handle's other options, times each with HIP events after a warm-up run, and keeps the
- * fastest in the handle's options (waves_per_block; blocks_per_cu automatic).  These
- * choices do not change any result bit.  Writes the choice and its time (ms) when the
- * pointers are not NULL.  Allocates scratch for one copy of Y and T and synchronises
- * the stream; ROK4E_ECAPTURE inside a stream capture, ROK4E_EINVAL for n_cells == 0. */
+/* Launch tuner (autotuning of the persistent kernel's result-neutral launch choices):
+ * integrates a copy of the given batch (Y, T, p as for rok4e_integrate; the caller's
+ * arrays are not modified) with each candidate launch layout and keeps the fastest in the
+ * handle's options.  Candidates: every lane layout (lanes_per_cell 16, 32, 64) that holds
+ * the ns + 1 state rows and M Krylov vectors, at its largest block and at half of it, and
+ * for the layouts that have one the private-memory JVP gather (jvp_gather).  Each is timed
+ * with HIP events as the faster of two runs after a warm-up run.  Within a lane layout the
+ * choices do not change any result bit; across lane layouts the production sums add in
+ * another order (results agree to rounding).  The choice is kept in a process-wide cache
+ * keyed by (GPU architecture and compute-unit count, n_species, n_reactions, M,
+ * precision, method): a later call with the same key (on any handle) applies the cached
+ * choice without timing anything, unless force is non-zero.  Allocates scratch for one
+ * copy of Y and T, rebuilds the handle's tables for each lane layout and synchronises the
+ * stream; ROK4E_ECAPTURE inside a stream capture, ROK4E_EINVAL for n_cells == 0.  out may
+ * be NULL. */
 int rok4e_tune(int64_t n_cells, rok4e_mech* mech, const double* Y, const double* T, const double* p,
-               double dt, double rtol, double atol, int32_t* best_waves, float* best_ms, void* stream);
+               double dt, double rtol, double atol, int32_t force, rok4e_tune_result* out,
+               void* stream);
 
 /* ---- Splitting around the reaction substep (Sec. 3.3) ------------------------------
  * Model transport operator on a periodic nx x ny x nz grid of cubic cells (cell

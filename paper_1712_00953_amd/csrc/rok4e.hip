@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -94,7 +95,9 @@ constexpr int integrate_max_threads() { return ROWS == 1 ? 256 : 512; }
 // and takes the next cell from the queue, so the segments stay in step attempt by attempt
 // instead of the wave waiting for its slowest cell before any segment takes a new one; the
 // wave leaves the loop when none of its segments holds a cell.
-template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor>
+// GATHER: the Jacobian-vector products read the base concentrations from a per-basis
+// gather into lane-private memory instead of LDS (layouts with has_gather only).
+template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor, int GATHER = 0>
 __global__ void __launch_bounds__(integrate_max_threads<ROWS>(), occupancy<ROWS>())
     k_integrate(DevMech m, Launch P) {
   extern __shared__ __align__(16) char smem[];
@@ -115,11 +118,11 @@ __global__ void __launch_bounds__(integrate_max_threads<ROWS>(), occupancy<ROWS>
       c.status = 3;
       if constexpr (FORM == kFormConservative) {
         if (load_cell_cons<L, ROWS>(m, t, P, cell, lane, u, s)) {
-          c = integrate_cell<L, ROWS, MMAX, RT, FORM>(m, t, P, u, p, s, S, lane);
+          c = integrate_cell<L, ROWS, MMAX, RT, FORM, GATHER>(m, t, P, u, p, s, S, lane);
           store_cell_cons<L, ROWS>(m, P, cell, lane, u);
         }
       } else if (load_cell<L, ROWS>(m, P, cell, lane, u, s, p)) {
-        c = integrate_cell<L, ROWS, MMAX, RT>(m, t, P, u, p, s, S, lane, P.hio ? P.hio[cell] : 0.0);
+        c = integrate_cell<L, ROWS, MMAX, RT, FORM, GATHER>(m, t, P, u, p, s, S, lane, P.hio ? P.hio[cell] : 0.0);
         store_cell<L, ROWS>(m, P, cell, lane, u);
         if (P.hio) P.hio[cell] = c.hnext;
       }
@@ -173,7 +176,7 @@ __global__ void __launch_bounds__(integrate_max_threads<ROWS>(), occupancy<ROWS>
       }
     }
     if (!__any(cell >= 0)) break;
-    if (cell >= 0) cell_attempt<L, ROWS, MMAX, RT, FORM>(m, t, P, u, p, s, S, lane, c, fn, Q);
+    if (cell >= 0) cell_attempt<L, ROWS, MMAX, RT, FORM, GATHER>(m, t, P, u, p, s, S, lane, c, fn, Q);
   }
 }
 
@@ -366,6 +369,7 @@ using ArnoldiFn = void (*)(DevMech, Launch, double*, double*, int32_t*);
 struct Variant {
   int L, rows, mmax, prec;
   IntegrateFn integrate;
+  IntegrateFn integrate_gather;   // the same with the JVP base-concentration gather (or null)
   IntegrateFn integrate_cons;   // conservative variables (FP64 variants; null otherwise)
   IntegrateFn rkdp;
   AttemptFn attempt;
@@ -374,13 +378,20 @@ struct Variant {
 };
 
 template <int L, int ROWS, int MMAX, class RT>
+constexpr IntegrateFn gather_kernel() {
+  if constexpr (has_gather<L, ROWS, MMAX>()) return k_integrate<L, ROWS, MMAX, RT, kFormReactor, 1>;
+  else return nullptr;
+}
+
+template <int L, int ROWS, int MMAX, class RT>
 constexpr IntegrateFn cons_kernel() {
   if constexpr (sizeof(RT) == 8) return k_integrate<L, ROWS, MMAX, RT, kFormConservative>;
   else return nullptr;
 }
 
 #define ROK4E_VARIANT(Lv, Rv, Mv, T, P)                                                       \
-  Variant{Lv, Rv, Mv, P, k_integrate<Lv, Rv, Mv, T>, cons_kernel<Lv, Rv, Mv, T>(),             \
+  Variant{Lv, Rv, Mv, P, k_integrate<Lv, Rv, Mv, T>, gather_kernel<Lv, Rv, Mv, T>(),          \
+          cons_kernel<Lv, Rv, Mv, T>(),                                                        \
           k_rkdp<Lv, Rv, T>, k_attempt<Lv, Rv, Mv, T>,                                         \
           k_arnoldi<Lv, Rv, Mv, T>,                                                             \
           k_rhs<Lv, Rv, T>}
@@ -444,6 +455,7 @@ struct rok4e_mech {
   rok4e_options opt{};
   const Variant* var = nullptr;
   int cu_count = 0;
+  std::string arch;   // GPU architecture name (gcnArchName), part of the tuning-cache key
   size_t lds_per_block_max = 0;
   // host copy of the mechanism
   std::vector<double> W, cp, hf, par;          // par: 6 x nr
@@ -494,6 +506,8 @@ bool options_ok(const rok4e_options& o) {
   if (o.scheduling != ROK4E_PERSISTENT && o.scheduling != ROK4E_PER_ATTEMPT) return false;
   if (o.method != ROK4E_METHOD_ROK4E && o.method != ROK4E_METHOD_RKDP45) return false;
   if (o.cell_order != ROK4E_ORDER_HOT_FIRST && o.cell_order != ROK4E_ORDER_ARRAY) return false;
+  if (o.jvp_gather != ROK4E_GATHER_AUTO && o.jvp_gather != ROK4E_GATHER_LDS && o.jvp_gather != ROK4E_GATHER_PRIVATE)
+    return false;
   if (!std::isfinite(o.h0)) return false;
   return true;
 }
@@ -721,6 +735,12 @@ void launch_order(rok4e_mech* m, const double* T, int64_t n, int64_t segments, h
   P.order = order;
 }
 
+// The persistent ROK4E kernel of the handle's layout and gather option.
+IntegrateFn integrate_fn(const rok4e_mech* m) {
+  if (m->opt.jvp_gather == ROK4E_GATHER_PRIVATE && m->var->integrate_gather) return m->var->integrate_gather;
+  return m->var->integrate;
+}
+
 int check_state_args(int64_t n, rok4e_mech* mech, const void* Y, const void* T, const void* p) {
   if (!mech || n < 0) return ROK4E_EINVAL;
   if (n > 0 && (!Y || !T || !p)) return ROK4E_EINVAL;
@@ -783,6 +803,49 @@ int run_per_attempt(rok4e_mech* m, const Launch& P, const SegLayout& sl, int64_t
     cur ^= 1;
   }
   return ROK4E_OK;
+}
+
+// ------------------------------------------------------------- tuning cache ----
+// Choices of rok4e_tune, kept for the life of the process and shared by all handles:
+// key (GPU architecture, compute units, n_species, n_reactions, M, precision, method).
+using TuneKey = std::tuple<std::string, int, int, int, int, int, int>;
+struct TuneChoice {
+  int lanes, waves, blocks, gather;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneChoice> g_tune_cache;
+
+TuneKey tune_key(const rok4e_mech* m) {
+  return TuneKey{m->arch, m->cu_count, m->ns, m->nr, m->opt.M, m->opt.precision, m->opt.method};
+}
+
+bool tune_lookup(const TuneKey& k, TuneChoice* c) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const auto it = g_tune_cache.find(k);
+  if (it == g_tune_cache.end()) return false;
+  *c = it->second;
+  return true;
+}
+
+void tune_store(const TuneKey& k, const TuneChoice& c) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache[k] = c;
+}
+
+// Sets the handle's launch options to a choice (its other options unchanged) and builds
+// the tables of its layout.
+int apply_choice(rok4e_mech* m, const TuneChoice& c) {
+  rok4e_options o = m->opt;
+  o.lanes_per_cell = c.lanes;
+  o.waves_per_block = c.waves;
+  o.blocks_per_cu = c.blocks;
+  o.jvp_gather = c.gather;
+  const Variant* v = pick_variant(m->ns, o);
+  if (!v) return ROK4E_ENOTSUP;
+  m->opt = o;
+  m->var = v;
+  return ensure_image(m);
 }
 
 }  // namespace
@@ -879,6 +942,7 @@ int rok4e_mech_create(const rok4e_mech_desc* d, const rok4e_options* o, rok4e_me
     return ROK4E_EHIP;
   }
   m->cu_count = prop.multiProcessorCount;
+  m->arch = prop.gcnArchName;
   m->lds_per_block_max = prop.sharedMemPerBlock;
   // the static scratch of this device: its address is looked up here, once per device,
   // with the handle's device current
@@ -975,12 +1039,12 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
     m->last_n = n_cells;
     return ROK4E_OK;
   }
-  rc = shape_for(m, sl, n_cells, (const void*)m->var->integrate, true, &sh, nullptr, nullptr,
-                 integrate_waves(*m->var));
+  const IntegrateFn kern = integrate_fn(m);
+  rc = shape_for(m, sl, n_cells, (const void*)kern, true, &sh, nullptr, nullptr, integrate_waves(*m->var));
   if (rc) return rc;
   launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P, m->d_bins, m->d_order);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
-  hipLaunchKernelGGL(m->var->integrate, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
+  hipLaunchKernelGGL(kern, dim3(sh.grid), dim3(sh.block), sh.lds, st, m->dm, P);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e);
   m->last_n = n_cells;
@@ -1068,7 +1132,7 @@ int rok4e_integrate_static(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
   P.rej = rej;
   P.status = status;
   const bool rkdp = m->opt.method == ROK4E_METHOD_RKDP45;
-  const IntegrateFn kern = rkdp ? m->var->rkdp : m->var->integrate;
+  const IntegrateFn kern = rkdp ? m->var->rkdp : integrate_fn(m);
   LaunchShape sh;
   rc = shape_for(m, sl, n_cells, (const void*)kern, true, &sh, nullptr, nullptr, rkdp ? 4 : integrate_waves(*m->var));
   if (rc) return rc;
@@ -1083,13 +1147,48 @@ int rok4e_integrate_static(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
 }
 
 int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T, const double* p,
-               double dt, double rtol, double atol, int32_t* best_waves, float* best_ms, void* stream) {
+               double dt, double rtol, double atol, int32_t force, rok4e_tune_result* out, void* stream) {
   int rc = check_state_args(n_cells, m, Y, T, p);
   if (rc) return rc;
   if (n_cells == 0) return ROK4E_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(rtol > 0.0) || !(atol >= 0.0) || !std::isfinite(rtol) ||
+      !std::isfinite(atol))
+    return ROK4E_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ROK4E_ECAPTURE;
+  rok4e_tune_result res{};
+  const TuneKey key = tune_key(m);
+  TuneChoice cached{};
+  if (!force && tune_lookup(key, &cached)) {
+    rc = apply_choice(m, cached);
+    if (rc) return rc;
+    res.lanes_per_cell = cached.lanes;
+    res.waves_per_block = cached.waves;
+    res.blocks_per_cu = cached.blocks;
+    res.jvp_gather = cached.gather;
+    res.ms = cached.ms;
+    res.from_cache = 1;
+    if (out) *out = res;
+    return ROK4E_OK;
+  }
+  rc = ensure_workspace(m, n_cells, st);
+  if (rc) return rc;
+  // candidates, grouped by lane layout (each layout's tables are built once)
+  std::vector<TuneChoice> cand;
+  for (int L : {64, 32, 16}) {
+    rok4e_options o = m->opt;
+    o.lanes_per_cell = L;
+    const Variant* v = pick_variant(m->ns, o);
+    if (!v) continue;
+    const int wmax = integrate_waves(*v);
+    for (int wpb : {wmax, wmax / 2}) {
+      if (wpb < 1) continue;
+      cand.push_back(TuneChoice{L, wpb, 0, ROK4E_GATHER_LDS, 0.0f});
+      if (v->integrate_gather && m->opt.method == ROK4E_METHOD_ROK4E)
+        cand.push_back(TuneChoice{L, wpb, 0, ROK4E_GATHER_PRIVATE, 0.0f});
+    }
+  }
   const size_t ny = (size_t)m->ns * n_cells;
   double *Y2 = nullptr, *T2 = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1097,14 +1196,11 @@ int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T,
   if (e == hipSuccess) e = hipMalloc((void**)&T2, n_cells * sizeof(double));
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  const rok4e_options saved = m->opt;
-  int best = 0;
-  float best_t = 0.0f;
-  for (int wpb = 1; e == hipSuccess && rc == ROK4E_OK && wpb <= 4; ++wpb) {
-    m->opt.waves_per_block = wpb;
-    m->opt.blocks_per_cu = 0;
-    float ms = 0.0f;
-    for (int rep = 0; rep < 2 && e == hipSuccess && rc == ROK4E_OK; ++rep) {   // first: warm-up
+  // one timing: the faster of two runs after a warm-up run
+  auto time_once = [&](float* best) {
+    *best = 0.0f;
+    for (int rep = 0; rep < 3 && e == hipSuccess && rc == ROK4E_OK; ++rep) {
+      float ms = 0.0f;
       e = hipMemcpyAsync(Y2, Y, ny * sizeof(double), hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess) e = hipMemcpyAsync(T2, T, n_cells * sizeof(double), hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess) e = hipEventRecord(e0, st);
@@ -1112,24 +1208,50 @@ int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T,
       if (e == hipSuccess && rc == ROK4E_OK) e = hipEventRecord(e1, st);
       if (e == hipSuccess && rc == ROK4E_OK) e = hipEventSynchronize(e1);
       if (e == hipSuccess && rc == ROK4E_OK) e = hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0 && (rep == 1 || ms < *best)) *best = ms;
     }
-    if (e == hipSuccess && rc == ROK4E_OK && (best == 0 || ms < best_t)) {
-      best = wpb;
-      best_t = ms;
+  };
+  const rok4e_options saved = m->opt;
+  const Variant* saved_var = m->var;
+  float t_default = 0.0f;
+  time_once(&t_default);
+  TuneChoice best{};
+  bool have = false;
+  for (const TuneChoice& c : cand) {
+    if (e != hipSuccess || rc != ROK4E_OK) break;
+    rc = apply_choice(m, c);
+    if (rc) break;
+    float ms = 0.0f;
+    time_once(&ms);
+    if (e == hipSuccess && rc == ROK4E_OK && (!have || ms < best.ms)) {
+      best = c;
+      best.ms = ms;
+      have = true;
     }
-  }
-  m->opt = saved;
-  if (e == hipSuccess && rc == ROK4E_OK) {
-    m->opt.waves_per_block = best;
-    if (best_waves) *best_waves = best;
-    if (best_ms) *best_ms = best_t;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(Y2);
   (void)hipFree(T2);
-  if (e != hipSuccess) return hip_fail(e);
-  return rc;
+  if (e != hipSuccess || rc != ROK4E_OK || !have) {
+    m->opt = saved;
+    m->var = saved_var;
+    const int rc2 = ensure_image(m);
+    if (e != hipSuccess) return hip_fail(e);
+    return rc ? rc : (rc2 ? rc2 : ROK4E_EHIP);
+  }
+  rc = apply_choice(m, best);
+  if (rc) return rc;
+  tune_store(key, best);
+  res.lanes_per_cell = best.lanes;
+  res.waves_per_block = best.waves;
+  res.blocks_per_cu = best.blocks;
+  res.jvp_gather = best.gather;
+  res.ms = best.ms;
+  res.ms_default = t_default;
+  res.candidates = (int32_t)cand.size();
+  if (out) *out = res;
+  return ROK4E_OK;
 }
 
 int rok4e_rhs(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T, const double* p,

@@ -568,9 +568,13 @@ struct ConcCache {
 };
 
 // Iterations cached for a layout (0: the products read the base concentrations from LDS):
-// six for the one-row, M <= 8 layout (up to 384 reactions at 64 lanes).
+// with GATHER, six for the one-row, M <= 8 layout (up to 384 reactions at 64 lanes).
+// Whether the gather pays depends on the register pressure of the rest of the kernel, so
+// both forms are compiled and the launch tuner chooses.
+template <int L, int ROWS, int MMAX, int GATHER>
+constexpr int jvp_cache_iters() { return (GATHER && L == 64 && ROWS == 1 && MMAX == 8) ? 6 : 0; }
 template <int L, int ROWS, int MMAX>
-constexpr int jvp_cache_iters() { return (L == 64 && ROWS == 1 && MMAX == 8) ? 6 : 0; }
+constexpr bool has_gather() { return jvp_cache_iters<L, ROWS, MMAX, 1>() > 0; }
 
 template <int L, int ROWS, class RT, int NIT = 0>
 __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, const RhsBase& B,

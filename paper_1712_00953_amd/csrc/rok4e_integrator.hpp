@@ -69,7 +69,7 @@ __device__ __forceinline__ void rhs_forced(const DevMech& m, const MechLds& t, c
 // numerator in difference form.  Q holds this lane's rows of the orthonormal basis, H
 // (LDS) the M x M Hessenberg matrix; both FP64.  Returns M_eff.  Needs the base
 // evaluation of f at u (rhs with SAVE) just before.
-template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor>
+template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor, int GATHER = 0>
 __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const Launch& P,
                                        const double (&u)[ROWS],
                                        const double (&fn)[ROWS], const typename BaseOf<FORM>::type& B,
@@ -100,7 +100,7 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
   const double delta = sqrt(P.eps_fd * (1.0 + sqrt(seg_sum<L, ROWS>(sq))));
   const double rdelta = 1.0 / delta;
   // base concentrations of this lane's reactions, left in LDS by the base evaluation
-  constexpr int NIT = jvp_cache_iters<L, ROWS, MMAX>();
+  constexpr int NIT = jvp_cache_iters<L, ROWS, MMAX, GATHER>();
   ConcCache<NIT, RT> cache;
   const bool cached = NIT > 0 && m.nr <= NIT * L;
   if constexpr (NIT > 0) {
@@ -340,7 +340,7 @@ __device__ __forceinline__ bool cell_running(const Launch& P, CellState& c) {
 // readings: clipped last step, err_n = 1 before the first acceptance and updated on
 // acceptance, basis (fn, Q, the LDS copy of H, M_eff) reused after a rejection,
 // non-finite u* or err rejected.
-template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor>
+template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor, int GATHER = 0>
 __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& tab, const Launch& P,
                                              double (&u)[ROWS], double p, const double (&s)[ROWS],
                                              const SegLds<RT>& S, int lane, CellState& c,
@@ -360,7 +360,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
     RT wbase[ROWS];
     typename BaseOf<FORM>::type base;
     rhs_forced<L, ROWS, RT, true, FORM>(m, tab, u, p, s, fn, S, lane, &base, wbase);
-    c.Meff = arnoldi<L, ROWS, MMAX, RT, FORM>(m, tab, P, u, fn, base, wbase, Q, S, lane);
+    c.Meff = arnoldi<L, ROWS, MMAX, RT, FORM, GATHER>(m, tab, P, u, fn, base, wbase, Q, S, lane);
     c.basis_valid = 1;
   }
   unsigned piv;
@@ -460,7 +460,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
 }
 
 // Integrates the segment's cell over [0, dt] in place in u (all attempts).
-template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor>
+template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor, int GATHER = 0>
 __device__ __forceinline__ CellState integrate_cell(const DevMech& m, const MechLds& tab,
                                                     const Launch& P, double (&u)[ROWS], double p,
                                                     const double (&s)[ROWS], const SegLds<RT>& S,
@@ -468,7 +468,7 @@ __device__ __forceinline__ CellState integrate_cell(const DevMech& m, const Mech
   CellState c;
   cell_start(P, c, h0c);
   double fn[ROWS], Q[ROWS][MMAX];
-  while (cell_running(P, c)) cell_attempt<L, ROWS, MMAX, RT, FORM>(m, tab, P, u, p, s, S, lane, c, fn, Q);
+  while (cell_running(P, c)) cell_attempt<L, ROWS, MMAX, RT, FORM, GATHER>(m, tab, P, u, p, s, S, lane, c, fn, Q);
   return c;
 }
 

@@ -24,6 +24,7 @@ PERSISTENT, PER_ATTEMPT = 0, 1
 SPLIT_SIMPLER, SPLIT_STRANG = 0, 1
 METHOD_ROK4E, METHOD_RKDP45 = 0, 1
 ORDER_HOT_FIRST, ORDER_ARRAY = 0, 1
+GATHER_AUTO, GATHER_LDS, GATHER_PRIVATE = 0, 1, 2
 CELL_OK, CELL_MAX_ATTEMPTS, CELL_STEP_UNDERFLOW, CELL_BAD_INPUT = 0, 1, 2, 3
 
 EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "rok4e_set_options",
@@ -47,7 +48,13 @@ class Options(C.Structure):
                 ("fixed_steps", C.c_int32), ("lanes_per_cell", C.c_int32),
                 ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("scheduling", C.c_int32), ("method", C.c_int32), ("cell_order", C.c_int32),
-                ("h0", C.c_double)]
+                ("jvp_gather", C.c_int32), ("h0", C.c_double)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("lanes_per_cell", C.c_int32), ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("jvp_gather", C.c_int32), ("ms", C.c_float), ("ms_default", C.c_float),
+                ("candidates", C.c_int32), ("from_cache", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -92,8 +99,7 @@ def load():
         lib.rok4e_integrate_ex.argtypes = [i64, vp, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_conservative.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_static.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp]
-        lib.rok4e_tune.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, C.POINTER(C.c_int32),
-                                   C.POINTER(C.c_float), vp]
+        lib.rok4e_tune.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, C.c_int32, C.POINTER(TuneResult), vp]
         lib.rok4e_rhs.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
         lib.rok4e_transport.argtypes = [C.POINTER(Grid), C.c_int32, vp, vp, vp, vp]
         lib.rok4e_split_workspace_bytes.restype = C.c_size_t
@@ -132,10 +138,11 @@ def _check(rc, what):
 
 def options(M=4, precision=FP64, max_attempts=0, fixed_steps=0, lanes_per_cell=0,
             waves_per_block=0, blocks_per_cu=0, scheduling=PERSISTENT, method=METHOD_ROK4E,
-            h0=0.0, cell_order=None) -> Options:
+            h0=0.0, cell_order=None, jvp_gather=GATHER_AUTO) -> Options:
     order = ORDER_HOT_FIRST if cell_order is None else int(cell_order)
     return Options(int(M), int(precision), int(max_attempts), int(fixed_steps), int(lanes_per_cell),
-                   int(waves_per_block), int(blocks_per_cu), int(scheduling), int(method), order, float(h0))
+                   int(waves_per_block), int(blocks_per_cu), int(scheduling), int(method), order,
+                   int(jvp_gather), float(h0))
 
 
 def _ptr(t):
@@ -271,17 +278,18 @@ class Mech:
         _check(rc, "rok4e_integrate_conservative")
         self.n_last = n
 
-    def tune(self, Y, T, p, dt, rtol, atol, stream=None) -> tuple[int, float]:
-        """rok4e_tune: picks the fastest waves-per-block on a copy of this batch; returns
-        (waves_per_block, ms)."""
+    def tune(self, Y, T, p, dt, rtol, atol, force=False, stream=None) -> dict:
+        """rok4e_tune: times the candidate launch layouts on a copy of this batch (or takes
+        the cached choice for this mechanism size, M, precision and method) and keeps the
+        fastest in the handle's options; returns the outcome as a dict."""
         n = int(T.shape[0])
         for t, rows, name in ((Y, self.n_species, "Y"), (T, 1, "T"), (p, 1, "p")):
             _need(t, rows * n, name, rows=rows)
-        wv, ms = C.c_int32(0), C.c_float(0.0)
+        r = TuneResult()
         _check(load().rok4e_tune(n, self._h, _ptr(Y), _ptr(T), _ptr(p), float(dt), float(rtol), float(atol),
-                                 C.byref(wv), C.byref(ms), _stream(stream)), "rok4e_tune")
-        self.opts.waves_per_block = wv.value
-        return wv.value, ms.value
+                                 int(bool(force)), C.byref(r), _stream(stream)), "rok4e_tune")
+        self.opts = self.get_options()
+        return {k: getattr(r, k) for k, _ in TuneResult._fields_}
 
     def rhs(self, Y, T, p, dY, dT, stream=None):
         n = int(T.shape[0])

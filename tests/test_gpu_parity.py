@@ -405,20 +405,62 @@ def test_graph_capture_replays_match_eager(R, n, prec):
 
 
 def test_tune_leaves_inputs_and_results_unchanged(R):
+    """The launch tuner times every candidate layout on a copy of the batch (the inputs stay
+    as they were), keeps the fastest, and caches the choice per (GPU, mechanism size, M,
+    precision, method): a second handle of the same key takes it without timing.  The
+    tuned handle's results are deterministic and agree with the automatic layout's within
+    the layout bar (equal bits within a lane layout; another lane layout adds the
+    production sums in another order)."""
     import torch
-    w = synth.workload(2, a_scale=A_SCALE, n_cells=2048)
+    w = synth.workload(2, a_scale=A_SCALE, n_cells=8192)
     st = w.states
     m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
     before = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
     Y, T, p = dev_state(st)
-    wv, ms = m.tune(Y, T, p, w.dt, w.rtol, w.atol)
-    assert 1 <= wv <= 4 and ms > 0.0
-    assert m.get_options().waves_per_block == wv
+    r = m.tune(Y, T, p, w.dt, w.rtol, w.atol, force=True)
+    _report("tune", {k: float(v) if isinstance(v, float) else v for k, v in r.items()})
+    assert r["from_cache"] == 0 and r["candidates"] >= 3 and r["ms"] > 0.0 and r["ms_default"] > 0.0
+    o = m.get_options()
+    assert o.lanes_per_cell == r["lanes_per_cell"] and o.waves_per_block == r["waves_per_block"]
+    assert o.jvp_gather == r["jvp_gather"]
     np.testing.assert_array_equal(Y.cpu().numpy(), st.Y)
     np.testing.assert_array_equal(T.cpu().numpy(), st.T)
     after = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
-    for a, b in zip(before, after):
+    again = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    for a, b in zip(after, again):
         np.testing.assert_array_equal(a, b)
+    mx, _ = normalized(after, before, w.rtol, w.atol)
+    assert relative(after, before) <= 1e-10 and mx <= 1e-6
+    assert np.all(after[2] == before[2]) and np.all(after[3] == before[3])
+    # a second handle with the same key: the cached choice, nothing timed
+    m2 = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    r2 = m2.tune(Y, T, p, w.dt, w.rtol, w.atol)
+    assert r2["from_cache"] == 1 and r2["candidates"] == 0
+    assert (r2["lanes_per_cell"], r2["waves_per_block"], r2["jvp_gather"]) == \
+        (r["lanes_per_cell"], r["waves_per_block"], r["jvp_gather"])
+    o2 = m2.get_options()
+    assert (o2.lanes_per_cell, o2.waves_per_block, o2.jvp_gather) == \
+        (o.lanes_per_cell, o.waves_per_block, o.jvp_gather)
+    cached = gpu_integrate(m2, st, w.dt, w.rtol, w.atol)
+    for a, b in zip(after, cached):
+        np.testing.assert_array_equal(a, b)
+    m.close()
+    m2.close()
+
+
+@pytest.mark.parametrize("gather", [1, 2])
+def test_jvp_gather_is_bitwise_neutral(R, gather):
+    """The private-memory gather of the base concentrations only moves where the JVPs read
+    them from: results equal the LDS reads' bit for bit (64-lane layout, M = 8)."""
+    w = synth.workload(2, a_scale=A_SCALE, n_cells=4096)
+    st = w.states
+    ref = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT, lanes_per_cell=64)
+    a = gpu_integrate(ref, st, w.dt, w.rtol, w.atol)
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT, lanes_per_cell=64, jvp_gather=gather)
+    b = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    ref.close()
     m.close()
 
 
