@@ -602,6 +602,9 @@ def main():
                         "tuning": mixed["tuning"],
                         "tflops_fp64_equivalent": mixed["tflops"],
                         "max_rel_err_vs_fp64": float(max(relY.max(), relT.max())),
+                        "bar_rel_err": 1e-5,
+                        "cells_above_bar": int((rel_cell > 1e-5).sum()),
+                        "within_bar": bool(rel_cell.max() <= 1e-5),
                         "p99_rel_err_vs_fp64": float(np.percentile(relY, 99)),
                         "same_step_sequence_frac": float(same.mean()),
                         "max_rel_err_vs_fp64_same_steps": float(rel_cell[same].max()) if same.any() else None,

@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(256, 2) k_rhs(DevMech m, Launch P, double* dY,
       const int r = i * L + lane;
       u[i] = r < ns ? P.Y[(int64_t)r * n + cell] : (r == ns ? P.T[cell] : 0.0);
     }
-    RT w[ROWS];
+    double w[ROWS];
     rhs<L, ROWS, RT, false>(m, t, u, P.p[cell], f, S.r, lane, nullptr, w);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(256, 2) k_arnoldi(DevMech m, Launch P, double*
     double u[ROWS], s[ROWS], fn[ROWS], p;
     load_cell<L, ROWS>(m, P, cell, lane, u, s, p);
     RhsBase base;
-    RT w[ROWS];
+    double w[ROWS];
     rhs_forced<L, ROWS, RT, true>(m, t, u, p, s, fn, S, lane, &base, w);
     for (int i = 0; i < MMAX * MMAX; ++i) S.H[i] = 0.0;
     lds_sync();
@@ -532,10 +532,10 @@ const Variant* pick_variant(int ns, const rok4e_options& o, int extra = 1) {
   return best;
 }
 
-// Per-segment LDS: concentrations and increments [2][LP] in the rate type, the production
-// accumulators [LP] in FP64 (two copies LP + 8 entries apart in the mixed form), the
-// rate-constant pairs [NRP] in the rate type, H, LU [MMAX^2] and 1/diag(U) [MMAX] in
-// FP64.
+// Per-segment LDS: concentrations [LP] in the rate type, their increments [LP] in FP64,
+// the production accumulators [LP] in FP64 (two copies LP + 8 entries apart in the mixed
+// form), the rate-constant pairs [NRP] in the rate type, H, LU [MMAX^2] and 1/diag(U)
+// [MMAX] in FP64.
 struct SegLayout {
   int bytes, off_k, off_H, off_LU, off_rdiag;
 };
@@ -550,8 +550,9 @@ SegLayout seg_layout(int nr, const Variant& v) {
   const int rt = rate_bytes(v.prec);
   const int lp = v.L * v.rows;
   SegLayout s{};
-  // concentrations and increments, accumulators (two copies in the mixed form)
-  int off = al16(2 * lp * rt + (rt == 4 ? 2 * lp + 8 : lp) * 8);
+  // concentrations (rate type), FP64 increments, accumulators (two copies in the mixed
+  // form)
+  int off = al16(lp * rt + lp * 8 + (rt == 4 ? 2 * lp + 8 : lp) * 8);
   s.off_k = off;
   off = al16(off + n_rx_padded(nr) * 2 * rt);
   s.off_H = off;
@@ -588,10 +589,7 @@ int build_image(rok4e_mech* m, const Variant* var, DevMech* dm, void** d_image, 
   const int off_spec = al16(3 * nrp * 16);
   const int off_rxo = al16(off_spec + 4 * lp * 8);
   const int off_spos = al16(off_rxo + nrp * 8);
-  // mixed precision: (b_f, E_f, b_r, E_r) once more in FP32 for the Jacobian-vector
-  // products
-  const int off_bE32 = rb == 4 ? al16(off_spos + lp * 4) : 0;
-  const int bytes = rb == 4 ? al16(off_bE32 + nrp * 16) : al16(off_spos + lp * 4);
+  const int bytes = al16(off_spos + lp * 4);
   std::vector<char> img(bytes, 0);
   // (ln A_f, ln A_r), (b_f, E_f), (b_r, E_r); m->par holds ln A_f, b_f, E_f, ln A_r,
   // b_r, E_r, each [nr]
@@ -620,23 +618,13 @@ int build_image(rok4e_mech* m, const Variant* var, DevMech* dm, void** d_image, 
   }
   int* spos = (int*)(img.data() + off_spos);
   for (int r = 0; r < lp; ++r) spos[r] = r < ns ? pl.pos[r] : ns;
-  if (off_bE32) {
-    float* be = (float*)(img.data() + off_bE32);
-    for (int q = 0; q < nr; ++q) {
-      const int j = pl.order[q];
-      be[4 * q] = (float)m->par[1 * nr + j];
-      be[4 * q + 1] = (float)m->par[2 * nr + j];
-      be[4 * q + 2] = (float)m->par[4 * nr + j];
-      be[4 * q + 3] = (float)m->par[5 * nr + j];
-    }
-  }
   if (*d_image) (void)hipFree(*d_image);
   *d_image = nullptr;
   *image_key = -1;
   hipError_t e = hipMalloc(d_image, bytes);
   if (e == hipSuccess) e = hipMemcpy(*d_image, img.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e);
-  *dm = DevMech{ns, nr, nrp, lp, off_spec, off_rxo, off_spos, off_bE32, bytes, (const int4*)*d_image};
+  *dm = DevMech{ns, nr, nrp, lp, off_spec, off_rxo, off_spos, bytes, (const int4*)*d_image};
   *image_key = key;
   return ROK4E_OK;
 }

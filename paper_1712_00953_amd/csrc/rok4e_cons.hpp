@@ -137,7 +137,7 @@ __device__ __forceinline__ void rhs_diff_cons(const DevMech& m, const MechLds& t
     const int r = i * L + lane;
     if (r < ns) {
       const int q = (ROWS == 1 ? t.rspos : t.spos[r]);
-      S.spc[LP + q] = 1e-6 * du[i] * (ROWS == 1 ? t.rinvW : t.invW[r]);
+      *inc_at<LP, double>((char*)S.spc, q * sizeof(double)) = 1e-6 * du[i] * (ROWS == 1 ? t.rinvW : t.invW[r]);
       acc_clear<LP, double>((char*)S.spc, q * sizeof(double));
     }
   }

@@ -57,7 +57,7 @@ constexpr double E1 = BH1 - B1, E2 = BH2 - B2, E3 = BH3 - 0.0, E4 = 0.0 - B4;
 // order of the production sums).
 struct DevMech {
   int ns, nr, nrp, lp;
-  int off_spec, off_rxo, off_spos, off_bE32, image_bytes;   // off_bE32: 0 when absent
+  int off_spec, off_rxo, off_spos, image_bytes;
   const int4* image;
 };
 
@@ -67,7 +67,6 @@ struct MechLds {
   const double* W; const double* invW; const double* cp; const double* hf;
   const uint2* rxo;
   const int* spos;
-  const float4* bE32;   // (b_f, E_f, b_r, E_r) in FP32, mixed-precision images only
   // this lane's state row (lane % L) of W, 1/W, cp, hf and the species position, read
   // once at kernel start: the one-row layouts take them from registers (or private
   // memory) instead of LDS in every evaluation
@@ -108,7 +107,6 @@ __device__ __forceinline__ MechLds load_mech_lds(const DevMech& m, char* lds) {
   t.W = sp; t.invW = sp + m.lp; t.cp = sp + 2 * m.lp; t.hf = sp + 3 * m.lp;
   t.rxo = (const uint2*)(lds + m.off_rxo);
   t.spos = (const int*)(lds + m.off_spos);
-  t.bE32 = m.off_bE32 ? (const float4*)(lds + m.off_bE32) : nullptr;
   const int r0 = (int)(threadIdx.x % L);
   t.rW = t.W[r0]; t.rinvW = t.invW[r0]; t.rcp = t.cp[r0]; t.rhf = t.hf[r0]; t.rspos = t.spos[r0];
   return t;
@@ -372,20 +370,21 @@ __device__ __forceinline__ double rcp(double x) {
 // -------------------------------------------------------- right-hand side ----
 
 // Per-segment LDS scratch of the right-hand side.  spc holds the concentrations of the
-// base state and their increments (difference evaluation), LP entries each in the rate
-// type, followed by the FP64 production accumulators (FP64 in both precisions): species k
-// sits at spc[k], spc[LP + k] and acc(k) (consecutive species fall in different LDS
-// banks).  In the mixed form the accumulators come in two copies, LP + 8 entries apart
-// (half the banks over): the reaction lanes of even index add into the first, those of
-// odd index into the second, and a species' production is the sum of its two entries.
-// Two lanes of one accumulate instruction that add into the same address are serialised
-// by the LDS at a cost well above that of a bank conflict, and with the copies
-// neighbouring lanes never do.  The FP64 layout keeps one copy: the second does not fit
-// beside three blocks per CU.  Entry ns is the absent reaction slot: concentration 1,
-// increment 0, accumulators never read.
+// base state (LP entries in the rate type), then their FP64 increments for the difference
+// evaluation (LP entries), then the FP64 production accumulators: species k sits at
+// spc[k], inc[k] and acc(k) (consecutive species fall in different LDS banks).  In the
+// mixed form the accumulators come in two copies, LP + 8 entries apart (half the banks
+// over): the reaction lanes of even index add into the first, those of odd index into the
+// second, and a species' production is the sum of its two entries.  Two lanes of one
+// accumulate instruction that add into the same address are serialised by the LDS at a
+// cost well above that of a bank conflict, and with the copies neighbouring lanes never
+// do.  The FP64 layout keeps one copy: the second does not fit beside three blocks per CU.
+// Entry ns is the absent reaction slot: concentration 1, increment 0, accumulators never
+// read.
 template <class RT>
 struct RhsLds {
-  RT* spc;                        // [2][LP] rate type, then double [LP] (x2 + 8 mixed)
+  RT* spc;                        // [LP] rate type, then double [LP] increments, then
+                                  // double [LP] accumulators (x2 + 8 mixed)
   typename Pair2<RT>::type* k;    // [NRP] (k_f, k_r) of the base state
 };
 
@@ -396,11 +395,22 @@ constexpr int acc_copies() { return sizeof(RT) == 4 ? 2 : 1; }
 template <int LP>
 constexpr unsigned acc_copy_bytes() { return (LP + 8) * sizeof(double); }
 
+// FP64 increment of the species at byte offset off (species x sizeof(RT)) of the
+// concentration array that starts at rb.
+template <int LP, class RT>
+__device__ __forceinline__ double* inc_at(char* rb, unsigned off) {
+  return (double*)(rb + LP * sizeof(RT) + off * (sizeof(double) / sizeof(RT)));
+}
+template <int LP, class RT>
+__device__ __forceinline__ double inc_read(const char* rb, unsigned off) {
+  return *(const double*)(rb + LP * sizeof(RT) + off * (sizeof(double) / sizeof(RT)));
+}
+
 // Accumulator (first copy) of the species at byte offset off (species x sizeof(RT)) of the
 // concentration array that starts at rb.
 template <int LP, class RT>
 __device__ __forceinline__ double* acc_at(char* rb, unsigned off) {
-  return (double*)(rb + 2 * LP * sizeof(RT) + off * (sizeof(double) / sizeof(RT)));
+  return (double*)(rb + LP * sizeof(RT) + LP * sizeof(double) + off * (sizeof(double) / sizeof(RT)));
 }
 
 // Clears the accumulator copies of a species.
@@ -468,8 +478,8 @@ __device__ __forceinline__ void lds_add(RT* p, RT v) {
 // reaction (rb: the lane's accumulator base, acc_base): a repeated species receives the
 // term twice, a species on both sides -q and +q.  An absent slot adds into the
 // accumulator of entry ns, which is never read.
-template <int LP, class RT>
-__device__ __forceinline__ void scatter_rate(char* rb, uint2 o, RT qr) {
+template <int LP, class RT, class V>
+__device__ __forceinline__ void scatter_rate(char* rb, uint2 o, V qr) {
   const double q = (double)qr;
   lds_add(acc_at<LP, RT>(rb, o.x & 0xFFFFu), -q);
   lds_add(acc_at<LP, RT>(rb, o.x >> 16), -q);
@@ -486,7 +496,7 @@ __device__ __forceinline__ void scatter_rate(char* rb, uint2 o, RT qr) {
 template <int L, int ROWS, class RT, bool SAVE>
 __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const double (&u)[ROWS],
                                     double p, double (&f)[ROWS], const RhsLds<RT>& S, int lane,
-                                    RhsBase* base, RT (&w)[ROWS]) {
+                                    RhsBase* base, double (&w)[ROWS]) {
   constexpr int LP = L * ROWS;
   const int ns = m.ns;
   const int sT = ns / L, lT = ns % L;
@@ -534,11 +544,15 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
-    const RT wk = r < ns ? (RT)(1e6 * acc_sum<LP, RT>((char*)S.spc, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(RT))) : (RT)0;
+    // the production rates, the species derivatives and the heat release are formed in
+    // FP64 from the FP64 sums in both forms: rounding them to FP32 would break the exact
+    // balance of the production rates (mass and elements), which the FP32 rates of
+    // progress keep
+    const double wk = r < ns ? 1e6 * acc_sum<LP, RT>((char*)S.spc, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(RT)) : 0.0;
     w[s] = wk;
-    f[s] = (double)((RT)(ROWS == 1 ? t.rW : t.W[r]) * wk * (RT)invrho);
-    const RT hk = (RT)((ROWS == 1 ? t.rhf : t.hf[r]) + (ROWS == 1 ? t.rcp : t.cp[r]) * (T - kTref));
-    ph[s] = (double)(hk * (RT)(ROWS == 1 ? t.rW : t.W[r]) * wk);
+    f[s] = (ROWS == 1 ? t.rW : t.W[r]) * wk * invrho;
+    const double hk = (ROWS == 1 ? t.rhf : t.hf[r]) + (ROWS == 1 ? t.rcp : t.cp[r]) * (T - kTref);
+    ph[s] = hk * (ROWS == 1 ? t.rW : t.W[r]) * wk;
   }
   const double hsum = seg_sum<L, ROWS>(ph);
   const double invD = rcp(rho * cpbar);
@@ -578,7 +592,7 @@ constexpr bool has_gather() { return jvp_cache_iters<L, ROWS, MMAX, 1>() > 0; }
 
 template <int L, int ROWS, class RT, int NIT = 0>
 __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, const RhsBase& B,
-                                         const RT (&w)[ROWS], const double (&u)[ROWS],
+                                         const double (&w)[ROWS], const double (&u)[ROWS],
                                          const double (&du)[ROWS], double (&df)[ROWS],
                                          const RhsLds<RT>& S, int lane,
                                          const ConcCache<NIT, RT>* cc = nullptr) {
@@ -608,7 +622,7 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
     const int r = s * L + lane;
     if (r < ns) {
       const int q = (ROWS == 1 ? t.rspos : t.spos[r]);
-      S.spc[LP + q] = (RT)(1e-6 * (rho1 * du[s] + drho * u[s]) * (ROWS == 1 ? t.rinvW : t.invW[r]));
+      *inc_at<LP, RT>((char*)S.spc, q * sizeof(RT)) = 1e-6 * (rho1 * du[s] + drho * u[s]) * (ROWS == 1 ? t.rinvW : t.invW[r]);
       acc_clear<LP, RT>((char*)S.spc, q * sizeof(RT));
     }
   }
@@ -618,32 +632,27 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
   char* ab = acc_base<LP, RT>(rb, lane);
   lds_sync();
   // one reaction: rate-constant increments, concentration products with increments,
-  // d q, scattered
-  auto diff_rx = [&](int j, const uint2 o, RT ca, RT cb, RT cc_, RT cd) {
-    // the exponents' increments b dlnT - E d(1/RT); the mixed form reads b and E from
-    // the FP32 table (half the bytes; its increments are FP32 anyway)
-    double dlf, dlr;
-    if constexpr (sizeof(RT) == 4) {
-      const float4 be = t.bE32[j];
-      dlf = (double)be.x * dlnT - (double)be.y * dinvRT;
-      dlr = (double)be.z * dlnT - (double)be.w * dinvRT;
-    } else {
-      const double2 bEf = t.bEf[j], bEr = t.bEr[j];
-      dlf = bEf.x * dlnT - bEf.y * dinvRT;
-      dlr = bEr.x * dlnT - bEr.y * dinvRT;
-    }
+  // d q, scattered.  The increments and everything formed from them are FP64 in both
+  // forms (the perturbation and difference of the finite-difference product); the
+  // mixed form's base rate constants and concentrations are its FP32 values, exact in
+  // FP64.
+  auto diff_rx = [&](int j, const uint2 o, RT ca_, RT cb_, RT cc_, RT cd_) {
+    const double2 bEf = t.bEf[j], bEr = t.bEr[j];
+    const double dlf = bEf.x * dlnT - bEf.y * dinvRT;
+    const double dlr = bEr.x * dlnT - bEr.y * dinvRT;
     const auto kj = S.k[j];
-    const RT kf = kj.x, kr = kj.y;
-    const RT dkf = kf * (RT)expm1_small(dlf);
-    const RT dkr = kr * (RT)expm1_small(dlr);
-    const RT dca = *(const RT*)(rb + (o.x & 0xFFFFu) + LP * sizeof(RT));
-    const RT dcb = *(const RT*)(rb + (o.x >> 16) + LP * sizeof(RT));
-    const RT dcc = *(const RT*)(rb + (o.y & 0xFFFFu) + LP * sizeof(RT));
-    const RT dcd = *(const RT*)(rb + (o.y >> 16) + LP * sizeof(RT));
+    const double kf = (double)kj.x, kr = (double)kj.y;
+    const double dkf = kf * expm1_small(dlf);
+    const double dkr = kr * expm1_small(dlr);
+    const double ca = (double)ca_, cb = (double)cb_, cc = (double)cc_, cd = (double)cd_;
+    const double dca = inc_read<LP, RT>(rb, o.x & 0xFFFFu);
+    const double dcb = inc_read<LP, RT>(rb, o.x >> 16);
+    const double dcc = inc_read<LP, RT>(rb, o.y & 0xFFFFu);
+    const double dcd = inc_read<LP, RT>(rb, o.y >> 16);
     // products of concentrations with increments: d(ab) = (a + da) db + da b
-    const RT pf = ca * cb, dpf = (ca + dca) * dcb + dca * cb;
-    const RT pr = cc_ * cd, dpr = (cc_ + dcc) * dcd + dcc * cd;
-    const RT dq = ((kf + dkf) * dpf + dkf * pf) - ((kr + dkr) * dpr + dkr * pr);
+    const double pf = ca * cb, dpf = (ca + dca) * dcb + dca * cb;
+    const double pr = cc * cd, dpr = (cc + dcc) * dcd + dcc * cd;
+    const double dq = ((kf + dkf) * dpf + dkf * pf) - ((kr + dkr) * dpr + dkr * pr);
     scatter_rate<LP, RT>(ab, o, dq);
   };
   if constexpr (NIT > 0) {
@@ -669,7 +678,7 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
   for (int s = 0; s < ROWS; ++s) {
     const int r = s * L + lane;
     const double dw = r < ns ? 1e6 * acc_sum<LP, RT>((char*)S.spc, (ROWS == 1 ? t.rspos : t.spos[r]) * sizeof(RT)) : 0.0;
-    const double wk = (double)w[s];
+    const double wk = w[s];
     df[s] = (ROWS == 1 ? t.rW : t.W[r]) * (dw * invrho1 - wk * drho * B.invrho * invrho1);
     const double hk = (ROWS == 1 ? t.rhf : t.hf[r]) + (ROWS == 1 ? t.rcp : t.cp[r]) * (T - kTref), dhk = (ROWS == 1 ? t.rcp : t.cp[r]) * dT;
     ph[s] = (ROWS == 1 ? t.rW : t.W[r]) * ((hk + dhk) * dw + dhk * wk);

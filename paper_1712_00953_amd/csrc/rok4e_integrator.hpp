@@ -26,12 +26,12 @@ __device__ __forceinline__ SegLds<RT> seg_lds(char* seg, const Launch& P) {
   return S;
 }
 
-// Constant entry of the segment's scratch: the absent reaction slot (concentration 1,
-// increment 0).
+// Constant entries of the segment's scratch: the absent reaction slot (concentration 1,
+// FP64 increment 0).
 template <class RT>
 __device__ __forceinline__ void init_seg(const DevMech& m, const SegLds<RT>& S) {
   S.r.spc[m.ns] = (RT)1;
-  S.r.spc[m.lp + m.ns] = (RT)0;
+  ((double*)((char*)S.r.spc + m.lp * sizeof(RT)))[m.ns] = 0.0;
   lds_sync();
 }
 
@@ -52,7 +52,7 @@ template <int L, int ROWS, class RT, bool SAVE, int FORM = kFormReactor>
 __device__ __forceinline__ void rhs_forced(const DevMech& m, const MechLds& t, const double (&u)[ROWS],
                                            double p, const double (&s)[ROWS], double (&f)[ROWS],
                                            const SegLds<RT>& S, int lane,
-                                           typename BaseOf<FORM>::type* base, RT (&w)[ROWS]) {
+                                           typename BaseOf<FORM>::type* base, double (&w)[ROWS]) {
   if constexpr (FORM == kFormConservative) {
     static_assert(sizeof(RT) == 8, "the conservative form is FP64 only");
     rhs_cons<L, ROWS, SAVE>(m, t, u, s, f, S.r, lane, base, w);
@@ -73,7 +73,7 @@ template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor, int GATH
 __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const Launch& P,
                                        const double (&u)[ROWS],
                                        const double (&fn)[ROWS], const typename BaseOf<FORM>::type& B,
-                                       const RT (&w)[ROWS], double (&Q)[ROWS][MMAX],
+                                       const double (&w)[ROWS], double (&Q)[ROWS][MMAX],
                                        const SegLds<RT>& S, int lane) {
   const int N = state_rows<FORM>(m);
   int Meff = P.M < N ? P.M : N;
@@ -357,7 +357,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
   }
   const double hprop = c.h;
   if (!c.basis_valid) {
-    RT wbase[ROWS];
+    double wbase[ROWS];
     typename BaseOf<FORM>::type base;
     rhs_forced<L, ROWS, RT, true, FORM>(m, tab, u, p, s, fn, S, lane, &base, wbase);
     c.Meff = arnoldi<L, ROWS, MMAX, RT, FORM, GATHER>(m, tab, P, u, fn, base, wbase, Q, S, lane);
@@ -374,7 +374,7 @@ __device__ __forceinline__ void cell_attempt(const DevMech& m, const MechLds& ta
   }
   double k1[ROWS], k2[ROWS], k3[ROWS], k4[ROWS];
   double corr[ROWS], F[ROWS], arg[ROWS], fs[ROWS];
-  RT wtmp[ROWS];
+  double wtmp[ROWS];
   // Stage 1: F1 = f_n.
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) corr[i] = 0.0;
@@ -499,7 +499,7 @@ __device__ __forceinline__ CellState rkdp_cell(const DevMech& m, const MechLds& 
   CellState c;
   cell_start(P, c);
   double k1[ROWS], k2[ROWS], k3[ROWS], k4[ROWS], k5[ROWS], k6[ROWS], k7[ROWS], arg[ROWS];
-  RT wt[ROWS];
+  double wt[ROWS];
   rhs_forced<L, ROWS, RT, false>(m, tab, u, p, s, k1, S, lane, nullptr, wt);
   while (cell_running(P, c)) {
     double h = c.h;
