@@ -18,12 +18,18 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # every expression.  Comparing the two builds measures how far rounding alone moves the
 # method's result (the envelope that GPU-vs-oracle differences are held to).
 _LIB_FMA = os.path.join(_HERE, "liboracle_fma.so")
+# The same source built with AddressSanitizer and UndefinedBehaviorSanitizer (host code
+# only), for the sanitizer test; loaded in place of the plain build when ORACLE_LIB names
+# it (the process must have the ASan runtime preloaded).
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
 
 CXXFLAGS = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
             "-shared", "-fPIC"]
 CXXFLAGS_FMA = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=fast", "-mfma", "-fopenmp",
                 "-shared", "-fPIC"]
 LIBS = ["-lquadmath"]
+CXXFLAGS_SAN = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fno-fast-math", "-ffp-contract=off",
+                "-fopenmp", "-shared", "-fPIC", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
 # finite difference (difference form), complex step, exact (linear), finite difference
 # evaluated literally as the difference of two rounded right-hand sides
@@ -54,6 +60,18 @@ class OrcOpts(C.Structure):
                 ("max_attempts", C.c_int32), ("eps_fd", C.c_double), ("h0", C.c_double)]
 
 
+def build_sanitized(verbose: bool = False) -> str:
+    """Compile the sanitizer build of the oracle (g++, host code; rebuilt when stale)."""
+    if os.path.exists(_LIB_SAN) and os.path.getmtime(_LIB_SAN) >= os.path.getmtime(_SRC):
+        return _LIB_SAN
+    cmd = ["g++", *CXXFLAGS_SAN, "-o", _LIB_SAN + ".tmp", _SRC, *LIBS]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_SAN + ".tmp", _LIB_SAN)
+    return _LIB_SAN
+
+
 _lib = None
 _lib_fma = None
 
@@ -61,6 +79,10 @@ _lib_fma = None
 def lib(fma: bool = False):
     global _lib, _lib_fma
     if _lib is None:
+        override = os.environ.get("ORACLE_LIB")
+        if override:
+            _lib = _lib_fma = C.CDLL(override)
+            return _lib
         stale = [p for p in (_LIB, _LIB_FMA)
                  if not os.path.exists(p) or os.path.getmtime(p) < os.path.getmtime(_SRC)]
         if stale:
