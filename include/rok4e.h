@@ -138,12 +138,17 @@ typedef struct {
   int32_t from_cache;      /* 1: the choice came from the tuning cache and nothing was timed */
 } rok4e_tune_result;
 
+/* Bins of the attempt histogram: bin 0 counts cells with no attempt (invalid input), bin
+ * b >= 1 cells with 2^(b-1) <= accepted + rejected < 2^b (the last bin also takes more). */
+#define ROK4E_HIST_BINS 22
+
 typedef struct {
   int64_t n_cells;        /* cells of the last integrate call */
   int64_t accepted;       /* accepted attempts, summed over cells */
   int64_t rejected;       /* rejected attempts, summed over cells */
   int64_t max_attempts;   /* largest accepted + rejected of any cell */
   int64_t status_count[4];/* cells per ROK4E_CELL_* status */
+  int64_t attempt_histogram[ROK4E_HIST_BINS]; /* cells per attempt-count bin (above) */
 } rok4e_stats;
 
 /* Fills *o with the defaults (M = 4, FP64, automatic layout, persistent). */

@@ -1410,8 +1410,12 @@ int rok4e_get_stats(rok4e_mech* m, rok4e_stats* out, void* stream) {
   for (int64_t i = 0; i < n; ++i) {
     out->accepted += a[i];
     out->rejected += r[i];
-    out->max_attempts = std::max<int64_t>(out->max_attempts, (int64_t)a[i] + r[i]);
+    const int64_t att = (int64_t)a[i] + r[i];
+    out->max_attempts = std::max<int64_t>(out->max_attempts, att);
     if (s[i] >= 0 && s[i] < 4) out->status_count[s[i]]++;
+    int bin = 0;
+    while (bin < ROK4E_HIST_BINS - 1 && att >= ((int64_t)1 << bin)) ++bin;
+    out->attempt_histogram[bin]++;
   }
   return ROK4E_OK;
 }

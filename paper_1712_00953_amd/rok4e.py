@@ -62,9 +62,13 @@ class Grid(C.Structure):
                 ("vel", C.c_double), ("diff", C.c_double)]
 
 
+HIST_BINS = 22
+
+
 class Stats(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("accepted", C.c_int64), ("rejected", C.c_int64),
-                ("max_attempts", C.c_int64), ("status_count", C.c_int64 * 4)]
+                ("max_attempts", C.c_int64), ("status_count", C.c_int64 * 4),
+                ("attempt_histogram", C.c_int64 * HIST_BINS)]
 
 
 class Rok4eError(RuntimeError):
@@ -330,7 +334,8 @@ class Mech:
         s = Stats()
         _check(load().rok4e_get_stats(self._h, C.byref(s), _stream(stream)), "rok4e_get_stats")
         return dict(n_cells=s.n_cells, accepted=s.accepted, rejected=s.rejected,
-                    max_attempts=s.max_attempts, status_count=list(s.status_count))
+                    max_attempts=s.max_attempts, status_count=list(s.status_count),
+                    attempt_histogram=list(s.attempt_histogram))
 
     def cell_stats(self, acc, rej, status, stream=None):
         """Copies per-cell counts of the last call into int32 tensors (host or device)."""

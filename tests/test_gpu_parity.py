@@ -591,6 +591,11 @@ def test_full_batch_sampled(R, orc, cfg, n_check):
     assert d["rel"] <= max(1e-10, 4 * env["env_rel"])
     assert d["match_frac"] >= match_floor(env["env_match"], n_check)
     assert d["sumY_drift"] <= 1e-9
+    # the attempt histogram of rok4e_get_stats counts every cell in its log2 bin
+    att = g[2].astype(np.int64) + g[3]
+    bins = np.where(att > 0, np.floor(np.log2(np.maximum(att, 1))).astype(int) + 1, 0)
+    hist = np.bincount(np.minimum(bins, R.HIST_BINS - 1), minlength=R.HIST_BINS)
+    assert m.stats()["attempt_histogram"] == hist.tolist()
     m.close()
 
 
