@@ -148,7 +148,7 @@ def run_gpu(w, precision, steps, warmup, R, torch, tune=True, graph_reps=10):
     graph_ms = graph_replays(m, w, Y0, T0, p, torch, stream) if graph_reps > 0 else None
     o = m.get_options()
     layout = {"lanes_per_cell": o.lanes_per_cell, "waves_per_block": o.waves_per_block,
-              "jvp_gather": ["auto", "lds", "private"][o.jvp_gather]}
+              "jvp_gather": ["auto", "lds", "private"][o.jvp_gather], "waves_per_simd": o.waves_per_simd}
     stats = m.stats()
     acc = torch.zeros(n, dtype=torch.int32)
     rej = torch.zeros(n, dtype=torch.int32)

@@ -113,8 +113,9 @@ typedef struct {
   int32_t fixed_steps;    /* 0: adaptive; n > 0: n equal steps, no error control */
   int32_t lanes_per_cell; /* 0: automatic; else 16, 32 or 64.  Changes the order in which
                              the production sums accumulate: results agree to rounding */
-  int32_t waves_per_block;/* 0: automatic; 1..8 waves of 64 lanes per block (bitwise neutral;
-                             layouts of one row slot per lane take at most 4) */
+  int32_t waves_per_block;/* 0: automatic; 1..16 waves of 64 lanes per block (bitwise neutral;
+                             at most 4 for one-slot layouts, 8 for two-slot ones, 16 with
+                             waves_per_simd = 4) */
   int32_t blocks_per_cu;  /* 0: automatic; persistent-grid blocks per compute unit
                              (bitwise neutral) */
   int32_t scheduling;     /* ROK4E_PERSISTENT or ROK4E_PER_ATTEMPT (bitwise neutral) */
@@ -123,6 +124,10 @@ typedef struct {
                              neutral; persistent schedule) */
   int32_t jvp_gather;     /* ROK4E_GATHER_AUTO (default), _LDS or _PRIVATE (bitwise neutral;
                              persistent schedule) */
+  int32_t waves_per_simd; /* 0 (automatic: 3 for one-slot layouts, 2 for others) or 4: the
+                             persistent ROK4E kernel compiled for four waves per SIMD (64-lane
+                             one-slot layouts with M <= 8, LDS reads; blocks of up to 16
+                             waves; bitwise neutral) */
   double h0;              /* first trial step; <= 0 means dt */
 } rok4e_options;
 
@@ -132,6 +137,7 @@ typedef struct {
   int32_t waves_per_block;
   int32_t blocks_per_cu;
   int32_t jvp_gather;
+  int32_t waves_per_simd;
   float ms;                /* time of one integration of the batch with the choice */
   float ms_default;        /* the same with the options the handle had before (0 on a cache hit) */
   int32_t candidates;      /* layouts timed (0 on a cache hit) */
@@ -255,7 +261,8 @@ int rok4e_integrate_static(int64_t n_cells, rok4e_mech* mech, double* Y, double*
  * arrays are not modified) with each candidate launch layout and keeps the fastest in the
  * handle's options.  Candidates: every lane layout (lanes_per_cell 16, 32, 64) that holds
  * the ns + 1 state rows and M Krylov vectors, at its largest block and at half of it, and
- * for the layouts that have one the private-memory JVP gather (jvp_gather).  Each is timed
+ * for the layouts that have them the private-memory JVP gather (jvp_gather) and the
+ * kernel held to four waves per SIMD (waves_per_simd).  Each is timed
  * with HIP events as the faster of two runs after a warm-up run.  Within a lane layout the
  * choices do not change any result bit; across lane layouts the production sums add in
  * another order (results agree to rounding).  The choice is kept in a process-wide cache

@@ -97,8 +97,10 @@ constexpr int integrate_max_threads() { return ROWS == 1 ? 256 : 512; }
 // wave leaves the loop when none of its segments holds a cell.
 // GATHER: the Jacobian-vector products read the base concentrations from a per-basis
 // gather into lane-private memory instead of LDS (layouts with has_gather only).
-template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor, int GATHER = 0>
-__global__ void __launch_bounds__(integrate_max_threads<ROWS>(), occupancy<ROWS>())
+// OCC4: registers held to four waves per SIMD (128 VGPRs, more spills) with blocks of up
+// to 16 waves, one-slot layouts (a launch-tuner candidate).
+template <int L, int ROWS, int MMAX, class RT, int FORM = kFormReactor, int GATHER = 0, int OCC4 = 0>
+__global__ void __launch_bounds__(OCC4 ? 1024 : integrate_max_threads<ROWS>(), OCC4 ? 4 : occupancy<ROWS>())
     k_integrate(DevMech m, Launch P) {
   extern __shared__ __align__(16) char smem[];
   const MechLds t = load_mech_lds<L>(m, smem);
@@ -370,6 +372,7 @@ struct Variant {
   int L, rows, mmax, prec;
   IntegrateFn integrate;
   IntegrateFn integrate_gather;   // the same with the JVP base-concentration gather (or null)
+  IntegrateFn integrate_occ4;     // the same held to four waves per SIMD (or null)
   IntegrateFn integrate_cons;   // conservative variables (FP64 variants; null otherwise)
   IntegrateFn rkdp;
   AttemptFn attempt;
@@ -384,6 +387,12 @@ constexpr IntegrateFn gather_kernel() {
 }
 
 template <int L, int ROWS, int MMAX, class RT>
+constexpr IntegrateFn occ4_kernel() {
+  if constexpr (L == 64 && ROWS == 1 && MMAX <= 8) return k_integrate<L, ROWS, MMAX, RT, kFormReactor, 0, 1>;
+  else return nullptr;
+}
+
+template <int L, int ROWS, int MMAX, class RT>
 constexpr IntegrateFn cons_kernel() {
   if constexpr (sizeof(RT) == 8) return k_integrate<L, ROWS, MMAX, RT, kFormConservative>;
   else return nullptr;
@@ -391,6 +400,7 @@ constexpr IntegrateFn cons_kernel() {
 
 #define ROK4E_VARIANT(Lv, Rv, Mv, T, P)                                                       \
   Variant{Lv, Rv, Mv, P, k_integrate<Lv, Rv, Mv, T>, gather_kernel<Lv, Rv, Mv, T>(),          \
+          occ4_kernel<Lv, Rv, Mv, T>(),                                                        \
           cons_kernel<Lv, Rv, Mv, T>(),                                                        \
           k_rkdp<Lv, Rv, T>, k_attempt<Lv, Rv, Mv, T>,                                         \
           k_arnoldi<Lv, Rv, Mv, T>,                                                             \
@@ -501,7 +511,8 @@ bool options_ok(const rok4e_options& o) {
   if (o.fixed_steps < 0) return false;
   if (o.lanes_per_cell != 0 && o.lanes_per_cell != 16 && o.lanes_per_cell != 32 && o.lanes_per_cell != 64)
     return false;
-  if (o.waves_per_block < 0 || o.waves_per_block > 8) return false;
+  if (o.waves_per_block < 0 || o.waves_per_block > 16) return false;
+  if (o.waves_per_simd != 0 && o.waves_per_simd != 3 && o.waves_per_simd != 4) return false;
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return false;
   if (o.scheduling != ROK4E_PERSISTENT && o.scheduling != ROK4E_PER_ATTEMPT) return false;
   if (o.method != ROK4E_METHOD_ROK4E && o.method != ROK4E_METHOD_RKDP45) return false;
@@ -723,10 +734,17 @@ void launch_order(rok4e_mech* m, const double* T, int64_t n, int64_t segments, h
   P.order = order;
 }
 
-// The persistent ROK4E kernel of the handle's layout and gather option.
+// The persistent ROK4E kernel of the handle's layout, gather and occupancy options, and its
+// largest block in waves.
 IntegrateFn integrate_fn(const rok4e_mech* m) {
   if (m->opt.jvp_gather == ROK4E_GATHER_PRIVATE && m->var->integrate_gather) return m->var->integrate_gather;
+  if (m->opt.waves_per_simd == 4 && m->var->integrate_occ4) return m->var->integrate_occ4;
   return m->var->integrate;
+}
+int integrate_fn_waves(const rok4e_mech* m) {
+  if (m->opt.jvp_gather == ROK4E_GATHER_PRIVATE && m->var->integrate_gather) return integrate_waves(*m->var);
+  if (m->opt.waves_per_simd == 4 && m->var->integrate_occ4) return 16;
+  return integrate_waves(*m->var);
 }
 
 int check_state_args(int64_t n, rok4e_mech* mech, const void* Y, const void* T, const void* p) {
@@ -798,7 +816,7 @@ int run_per_attempt(rok4e_mech* m, const Launch& P, const SegLayout& sl, int64_t
 // key (GPU architecture, compute units, n_species, n_reactions, M, precision, method).
 using TuneKey = std::tuple<std::string, int, int, int, int, int, int>;
 struct TuneChoice {
-  int lanes, waves, blocks, gather;
+  int lanes, waves, blocks, gather, simd;
   float ms;
 };
 std::mutex g_tune_mu;
@@ -829,6 +847,7 @@ int apply_choice(rok4e_mech* m, const TuneChoice& c) {
   o.waves_per_block = c.waves;
   o.blocks_per_cu = c.blocks;
   o.jvp_gather = c.gather;
+  o.waves_per_simd = c.simd;
   const Variant* v = pick_variant(m->ns, o);
   if (!v) return ROK4E_ENOTSUP;
   m->opt = o;
@@ -1028,7 +1047,7 @@ int rok4e_integrate_ex(int64_t n_cells, rok4e_mech* m, double* Y, double* T, con
     return ROK4E_OK;
   }
   const IntegrateFn kern = integrate_fn(m);
-  rc = shape_for(m, sl, n_cells, (const void*)kern, true, &sh, nullptr, nullptr, integrate_waves(*m->var));
+  rc = shape_for(m, sl, n_cells, (const void*)kern, true, &sh, nullptr, nullptr, integrate_fn_waves(m));
   if (rc) return rc;
   launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P, m->d_bins, m->d_order);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, m->d_queue);
@@ -1122,7 +1141,7 @@ int rok4e_integrate_static(int64_t n_cells, rok4e_mech* m, double* Y, double* T,
   const bool rkdp = m->opt.method == ROK4E_METHOD_RKDP45;
   const IntegrateFn kern = rkdp ? m->var->rkdp : integrate_fn(m);
   LaunchShape sh;
-  rc = shape_for(m, sl, n_cells, (const void*)kern, true, &sh, nullptr, nullptr, rkdp ? 4 : integrate_waves(*m->var));
+  rc = shape_for(m, sl, n_cells, (const void*)kern, true, &sh, nullptr, nullptr, rkdp ? 4 : integrate_fn_waves(m));
   if (rc) return rc;
   launch_order(m, T, n_cells, (int64_t)sh.grid * sh.segs_per_block, st, P, m->scratch + kScratchBins,
                (int32_t*)(m->scratch + kScratchOrder));
@@ -1155,6 +1174,7 @@ int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T,
     res.waves_per_block = cached.waves;
     res.blocks_per_cu = cached.blocks;
     res.jvp_gather = cached.gather;
+    res.waves_per_simd = cached.simd;
     res.ms = cached.ms;
     res.from_cache = 1;
     if (out) *out = res;
@@ -1172,10 +1192,12 @@ int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T,
     const int wmax = integrate_waves(*v);
     for (int wpb : {wmax, wmax / 2}) {
       if (wpb < 1) continue;
-      cand.push_back(TuneChoice{L, wpb, 0, ROK4E_GATHER_LDS, 0.0f});
+      cand.push_back(TuneChoice{L, wpb, 0, ROK4E_GATHER_LDS, 0, 0.0f});
       if (v->integrate_gather && m->opt.method == ROK4E_METHOD_ROK4E)
-        cand.push_back(TuneChoice{L, wpb, 0, ROK4E_GATHER_PRIVATE, 0.0f});
+        cand.push_back(TuneChoice{L, wpb, 0, ROK4E_GATHER_PRIVATE, 0, 0.0f});
     }
+    if (v->integrate_occ4 && m->opt.method == ROK4E_METHOD_ROK4E)
+      cand.push_back(TuneChoice{L, 16, 0, ROK4E_GATHER_LDS, 4, 0.0f});
   }
   const size_t ny = (size_t)m->ns * n_cells;
   double *Y2 = nullptr, *T2 = nullptr;
@@ -1235,6 +1257,7 @@ int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T,
   res.waves_per_block = best.waves;
   res.blocks_per_cu = best.blocks;
   res.jvp_gather = best.gather;
+  res.waves_per_simd = best.simd;
   res.ms = best.ms;
   res.ms_default = t_default;
   res.candidates = (int32_t)cand.size();

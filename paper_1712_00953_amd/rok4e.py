@@ -48,12 +48,13 @@ class Options(C.Structure):
                 ("fixed_steps", C.c_int32), ("lanes_per_cell", C.c_int32),
                 ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("scheduling", C.c_int32), ("method", C.c_int32), ("cell_order", C.c_int32),
-                ("jvp_gather", C.c_int32), ("h0", C.c_double)]
+                ("jvp_gather", C.c_int32), ("waves_per_simd", C.c_int32), ("h0", C.c_double)]
 
 
 class TuneResult(C.Structure):
     _fields_ = [("lanes_per_cell", C.c_int32), ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("jvp_gather", C.c_int32), ("ms", C.c_float), ("ms_default", C.c_float),
+                ("jvp_gather", C.c_int32), ("waves_per_simd", C.c_int32), ("ms", C.c_float),
+                ("ms_default", C.c_float),
                 ("candidates", C.c_int32), ("from_cache", C.c_int32)]
 
 
@@ -142,11 +143,11 @@ def _check(rc, what):
 
 def options(M=4, precision=FP64, max_attempts=0, fixed_steps=0, lanes_per_cell=0,
             waves_per_block=0, blocks_per_cu=0, scheduling=PERSISTENT, method=METHOD_ROK4E,
-            h0=0.0, cell_order=None, jvp_gather=GATHER_AUTO) -> Options:
+            h0=0.0, cell_order=None, jvp_gather=GATHER_AUTO, waves_per_simd=0) -> Options:
     order = ORDER_HOT_FIRST if cell_order is None else int(cell_order)
     return Options(int(M), int(precision), int(max_attempts), int(fixed_steps), int(lanes_per_cell),
                    int(waves_per_block), int(blocks_per_cu), int(scheduling), int(method), order,
-                   int(jvp_gather), float(h0))
+                   int(jvp_gather), int(waves_per_simd), float(h0))
 
 
 def _ptr(t):

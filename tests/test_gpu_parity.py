@@ -423,7 +423,7 @@ def test_tune_leaves_inputs_and_results_unchanged(R):
     assert r["from_cache"] == 0 and r["candidates"] >= 3 and r["ms"] > 0.0 and r["ms_default"] > 0.0
     o = m.get_options()
     assert o.lanes_per_cell == r["lanes_per_cell"] and o.waves_per_block == r["waves_per_block"]
-    assert o.jvp_gather == r["jvp_gather"]
+    assert o.jvp_gather == r["jvp_gather"] and o.waves_per_simd == r["waves_per_simd"]
     np.testing.assert_array_equal(Y.cpu().numpy(), st.Y)
     np.testing.assert_array_equal(T.cpu().numpy(), st.T)
     after = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
@@ -449,15 +449,17 @@ def test_tune_leaves_inputs_and_results_unchanged(R):
     m2.close()
 
 
-@pytest.mark.parametrize("gather", [1, 2])
-def test_jvp_gather_is_bitwise_neutral(R, gather):
+@pytest.mark.parametrize("gather,simd", [(1, 0), (2, 0), (1, 4)])
+def test_jvp_gather_is_bitwise_neutral(R, gather, simd):
     """The private-memory gather of the base concentrations only moves where the JVPs read
-    them from: results equal the LDS reads' bit for bit (64-lane layout, M = 8)."""
+    them from, and the kernel held to four waves per SIMD only spills more: results equal
+    the default kernel's bit for bit (64-lane layout, M = 8)."""
     w = synth.workload(2, a_scale=A_SCALE, n_cells=4096)
     st = w.states
     ref = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT, lanes_per_cell=64)
     a = gpu_integrate(ref, st, w.dt, w.rtol, w.atol)
-    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT, lanes_per_cell=64, jvp_gather=gather)
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT, lanes_per_cell=64, jvp_gather=gather,
+               waves_per_simd=simd)
     b = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
