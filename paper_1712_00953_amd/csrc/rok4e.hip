@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(256, occupancy<ROWS>()) k_attempt(DevMech m, L
 
 // f(u) for every cell (grid-stride over cells, one cell per segment).
 template <int L, int ROWS, class RT>
-__global__ void __launch_bounds__(256, 2) k_rhs(DevMech m, Launch P, double* dY, double* dT) {
+__global__ void __launch_bounds__(256, 4) k_rhs(DevMech m, Launch P, double* dY, double* dT) {
   extern __shared__ __align__(16) char smem[];
   const MechLds t = load_mech_lds<L>(m, smem);
   const int lane = (int)(threadIdx.x % L);
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(256, 2) k_rhs(DevMech m, Launch P, double* dY,
 
 // Arnoldi basis at every cell's state (diagnostics and step-level parity).
 template <int L, int ROWS, int MMAX, class RT>
-__global__ void __launch_bounds__(256, 2) k_arnoldi(DevMech m, Launch P, double* Qo, double* Ho,
+__global__ void __launch_bounds__(256, 3) k_arnoldi(DevMech m, Launch P, double* Qo, double* Ho,
                                                   int32_t* Mo) {
   extern __shared__ __align__(16) char smem[];
   const MechLds t = load_mech_lds<L>(m, smem);
@@ -340,8 +340,6 @@ __global__ void __launch_bounds__(256, 2) k_arnoldi(DevMech m, Launch P, double*
     RhsBase base;
     double w[ROWS];
     rhs_forced<L, ROWS, RT, true>(m, t, u, p, s, fn, S, lane, &base, w);
-    for (int i = 0; i < MMAX * MMAX; ++i) S.H[i] = 0.0;
-    lds_sync();
     double Q[ROWS][MMAX];
     const int Meff = arnoldi<L, ROWS, MMAX, RT>(m, t, P, u, fn, base, w, Q, S, lane);
 #pragma unroll
@@ -1271,10 +1269,13 @@ int rok4e_rhs(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T, 
   if (rc) return rc;
   if (n_cells > 0 && (!dY || !dT)) return ROK4E_EINVAL;
   if (n_cells == 0) return ROK4E_OK;
-  const SegLayout sl = seg_layout(m->nr, *m->var);
+  // f alone needs only the concentrations, increments and accumulators of each segment:
+  // the smaller footprint lets more segments share a compute unit
+  SegLayout sl = seg_layout(m->nr, *m->var);
+  sl.bytes = sl.off_k;
   Launch P = base_launch(m, n_cells, const_cast<double*>(Y), const_cast<double*>(T), p, nullptr, sl);
   LaunchShape sh;
-  rc = shape_for(m, sl, n_cells, (const void*)m->var->rhs, false, &sh);
+  rc = shape_for(m, sl, n_cells, (const void*)m->var->rhs, true, &sh);
   if (rc) return rc;
   hipLaunchKernelGGL(m->var->rhs, dim3(sh.grid), dim3(sh.block), sh.lds, (hipStream_t)stream, m->dm, P, dY, dT);
   const hipError_t e = hipGetLastError();
@@ -1290,7 +1291,7 @@ int rok4e_arnoldi(int64_t n_cells, rok4e_mech* m, const double* Y, const double*
   const SegLayout sl = seg_layout(m->nr, *m->var);
   Launch P = base_launch(m, n_cells, const_cast<double*>(Y), const_cast<double*>(T), p, nullptr, sl);
   LaunchShape sh;
-  rc = shape_for(m, sl, n_cells, (const void*)m->var->arnoldi, false, &sh);
+  rc = shape_for(m, sl, n_cells, (const void*)m->var->arnoldi, true, &sh);
   if (rc) return rc;
   hipLaunchKernelGGL(m->var->arnoldi, dim3(sh.grid), dim3(sh.block), sh.lds, (hipStream_t)stream, m->dm, P, Q, H,
                      Meff);

@@ -357,8 +357,27 @@ __device__ __forceinline__ float arrhenius(double lnA, double b, double E, doubl
 template <class V>
 __device__ __forceinline__ bool finite_(V x) { return __builtin_isfinite(x); }
 
-// 1/x for positive normal x: the hardware reciprocal refined by two Newton steps
-// (within about one ulp; used for cell-uniform quantities such as rho and T).
+// sqrt(x) and 1/sqrt(x) for positive x: the hardware reciprocal square root refined by two
+// Newton steps, the root from it with one correction step (each within about one ulp; for
+// the Arnoldi norms, in place of a square root and a division); the library routines for x
+// outside [2^-1000, 2^1000].
+__device__ __forceinline__ void sqrt_rsqrt(double x, double& root, double& rroot) {
+  if (!(x >= 0x1p-1000 && x <= 0x1p1000)) {   // far from the normal range: library routines
+    root = sqrt(x);
+    rroot = 1.0 / root;
+    return;
+  }
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  const double r = x * y;
+  root = fma(0.5 * y, fma(-r, r, x), r);
+  rroot = y;
+}
+
+// 1/x for normal x of either sign: the hardware reciprocal refined by two Newton steps
+// (within about one ulp; used for cell-uniform quantities such as rho and T, and the
+// pivots of the projected factorisation).
 __device__ __forceinline__ double rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);

@@ -90,9 +90,10 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
   double sq[ROWS];
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) sq[i] = fn[i] * fn[i];
-  const double beta = sqrt(seg_sum<L, ROWS>(sq));
-  if (beta == 0.0) return 0;
-  const double rbeta = 1.0 / beta;
+  const double beta2 = seg_sum<L, ROWS>(sq);
+  if (beta2 == 0.0) return 0;
+  double beta, rbeta;
+  sqrt_rsqrt(beta2, beta, rbeta);
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) Q[i][0] = fn[i] * rbeta;
 #pragma unroll
@@ -171,16 +172,16 @@ __device__ __forceinline__ int arnoldi(const DevMech& m, const MechLds& t, const
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) sq[i] = wv[i] * wv[i];
       const double hn2 = seg_sum<L, ROWS>(sq);
-      const double hn = sqrt(hn2);
-      // |J q_j| before the orthogonalization, from the orthogonal decomposition
-      // |w|^2 = sum_i h_ij^2 + h_{j+1,j}^2 (no separate reduction)
-      const double wn0 = sqrt(hsq + hn2);
-      if (!(hn > 1e-12 * wn0)) {
+      // |J q_j| before the orthogonalization from the orthogonal decomposition
+      // |w|^2 = sum_i h_ij^2 + h_{j+1,j}^2 (no separate reduction); the breakdown test
+      // |w_new| <= 1e-12 |w| compares the squares
+      if (!(hn2 > 1e-24 * (hsq + hn2))) {
         Meff = j + 1;
         break;
       }
+      double hn, rhn;
+      sqrt_rsqrt(hn2, hn, rhn);
       S.H[(j + 1) * MMAX + j] = hn;
-      const double rhn = 1.0 / hn;
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) Q[i][j + 1] = wv[i] * rhn;
     }
@@ -227,7 +228,7 @@ __device__ __forceinline__ bool lu_factor(const double* __restrict__ H, double h
     }
     const double akk = r[k];
     ok = ok && akk != 0.0;
-    const double rk = 1.0 / akk;
+    const double rk = rcp(akk);
     rdiag[k] = rk;
 #pragma unroll
     for (int j = k + 1; j < MMAX; ++j) LU[k * MMAX + j] = r[j];
