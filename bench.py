@@ -115,7 +115,7 @@ def graph_replays(m, w, Y0, T0, p, torch, stream, reps=10):
             "max_ms": float(np.max(times[1:]))}
 
 
-def run_gpu(w, precision, steps, warmup, R, torch, tune=True, graph_reps=10):
+def run_gpu(w, precision, steps, warmup, R, torch, tune=True, graph_reps=10, layout=None):
     """The timed integration of the batch.  With tune, the launch tuner first picks the
     launch layout on a copy of the same batch (outside the timed region)."""
     from paper_1712_00953_amd import workmodel
@@ -127,9 +127,9 @@ def run_gpu(w, precision, steps, warmup, R, torch, tune=True, graph_reps=10):
     p = torch.tensor(st.p, dtype=torch.float64, device=dev)
     # one private copy of the inputs per step, made before any timing
     copies = [(Y0.clone(), T0.clone()) for _ in range(warmup + steps)]
-    m = R.Mech(w.mech, M=w.M, precision=precision, max_attempts=200000)
+    m = R.Mech(w.mech, M=w.M, precision=precision, max_attempts=200000, **(layout or {}))
     m.reserve(n)
-    tuning = m.tune(Y0, T0, p, w.dt, w.rtol, w.atol) if tune else None
+    tuning = m.tune(Y0, T0, p, w.dt, w.rtol, w.atol) if tune and not layout else None
     stream = torch.cuda.current_stream()   # the stream the library launches on
     for i in range(warmup):
         m.integrate(copies[i][0], copies[i][1], p, w.dt, w.rtol, w.atol)
@@ -540,6 +540,9 @@ def main():
                     help="print the kernel source hash that a traffic measurement must carry")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the automatic launch layout without running the launch tuner first")
+    ap.add_argument("--layout", type=str, default=None,
+                    help="launch options as JSON (e.g. '{\"waves_per_simd\": 4}') for the headline "
+                         "integrations instead of tuning (profiling runs of the tuned kernel)")
     ap.add_argument("--study", action="store_true",
                     help="run only the efficiency study (ROK4E M = 4, 6, 8 vs Dormand-Prince 5(4) "
                          "over h_CFL = 1e-9 .. 1e-5) and print it as one JSON line")
@@ -564,14 +567,15 @@ def main():
         return
     w = synth.workload(2, a_scale=A_SCALE)
     log(f"workload {w.name}: {w.states.n_cells} cells, M={w.M}, dt={w.dt}")
+    layout = json.loads(args.layout) if args.layout else None
     fp64 = run_gpu(w, R.FP64, args.steps, args.warmup, R, torch, tune=not args.no_tune,
-                   graph_reps=0 if args.no_extras else 10)
+                   graph_reps=0 if args.no_extras else 10, layout=layout)
     log(f"fp64: {fp64['cells_per_s']:.4e} cells/s, {fp64['ms_per_step']:.2f} ms/step, "
         f"{fp64['attempts']} attempts/step, {fp64['tflops']:.3f} TFLOP/s")
     mixed = None
     if not args.no_mixed:
         mixed = run_gpu(w, R.MIXED, args.steps, args.warmup, R, torch, tune=not args.no_tune,
-                        graph_reps=0)
+                        graph_reps=0, layout=layout)
         log(f"mixed: {mixed['cells_per_s']:.4e} cells/s, {mixed['ms_per_step']:.2f} ms/step")
     subsystems = schedules = splitting = conservative = curve = stiff = None
     if not args.no_extras:
