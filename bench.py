@@ -4,7 +4,10 @@ One step = one reaction substep (Algorithm a:ROK4E over dt) for every cell of th
 with the cell states already resident in HBM.  Workload: the 53-species / 325-reaction
 synthetic mechanism on a 256 x 256 flame slice (65,536 cells), M = 8, dt = 1e-5 s,
 rtol = 1e-6, atol = 1e-12, pre-exponential factors scaled by 1e-8 (the calibrated
-mechanism; the literal draw is too stiff to integrate, see the design notes).
+mechanism, whose attempt counts span one to a few hundred per cell).  The literal draw of
+the generator (no multiplier; thousands to tens of thousands of attempts per cell) is
+timed beside it on the 9- and 53-species workloads, and so is the stiffer mechanism
+(multiplier 1e-5).
 
 Prints one JSON line: FP64 cell-integrations/s as `value`, the mixed-precision figure
 and speed-up beside it, the roofline of the integration kernel (algorithmic FP64
@@ -207,6 +210,52 @@ def run_stiff(R, torch, synth, a_scale=1e-5):
             "cells_per_s": n / t, "ms": t * 1e3, "attempts": s["accepted"] + s["rejected"],
             "max_attempts_cell": s["max_attempts"], "status_ok": s["status_count"][0],
             "tflops": tf, "frac_fp64_peak": tf / PEAK_FP64_TFLOPS, "tuning": tuning}
+
+
+def run_literal(R, torch, synth, tuning=None):
+    """The literal generator draw (pre-exponential factors log-uniform in [1e6, 1e14], no
+    multiplier) on the 9-species batch and on the 53-species flame slice: one FP64
+    integration each, timed with HIP events, in the headline's tuned layout (the tuner is
+    not run here: one integration of the flame slice takes about half a minute)."""
+    from paper_1712_00953_amd import workmodel
+    out = {}
+    for cfg in (1, 2):
+        w = synth.workload(cfg, a_scale=1.0)
+        st = w.states
+        n = st.n_cells
+        dev = torch.device("cuda:0")
+        Y = torch.tensor(st.Y, dtype=torch.float64, device=dev)
+        T = torch.tensor(st.T, dtype=torch.float64, device=dev)
+        p = torch.tensor(st.p, dtype=torch.float64, device=dev)
+        layout = {}
+        if cfg == 2 and tuning:
+            layout = {k: tuning[k] for k in ("lanes_per_cell", "waves_per_block", "jvp_gather",
+                                             "waves_per_simd")}
+        m = R.Mech(w.mech, M=w.M, max_attempts=1 << 22, **layout)
+        m.reserve(n)
+        stream = torch.cuda.current_stream()
+        t = timed_events(torch, stream, lambda: m.integrate(Y, T, p, w.dt, w.rtol, w.atol), 1)[0]
+        s = m.stats()
+        acc = torch.zeros(n, dtype=torch.int32)
+        rej = torch.zeros_like(acc)
+        sta = torch.zeros_like(acc)
+        m.cell_stats(acc, rej, sta)
+        torch.cuda.synchronize()
+        lanes = m.get_options().lanes_per_cell
+        m.close()
+        att = (acc + rej).numpy()
+        ops = workmodel.batch_ops(w.mech, w.M, s["accepted"], s["rejected"])
+        tf = ops["flops"] / t * 1e-12
+        out[f"{w.mech.n_species}sp"] = {
+            "workload": w.name + " (literal draw: A log-uniform in [1e6, 1e14])", "n_cells": n,
+            "ms": t * 1e3, "cells_per_s": n / t, "attempts": int(att.sum()),
+            "attempts_per_s": float(att.sum() / t),
+            "attempts_per_cell": {"min": int(att.min()), "p50": float(np.percentile(att, 50)),
+                                  "p95": float(np.percentile(att, 95)), "max": int(att.max()),
+                                  "mean": float(att.mean())},
+            "status_ok": s["status_count"][0], "lanes_per_cell": lanes, "tflops": tf,
+            "frac_fp64_peak": tf / PEAK_FP64_TFLOPS}
+    return out
 
 
 def run_subsystems(w, R, torch, reps=5):
@@ -577,11 +626,16 @@ def main():
         mixed = run_gpu(w, R.MIXED, args.steps, args.warmup, R, torch, tune=not args.no_tune,
                         graph_reps=0, layout=layout)
         log(f"mixed: {mixed['cells_per_s']:.4e} cells/s, {mixed['ms_per_step']:.2f} ms/step")
-    subsystems = schedules = splitting = conservative = curve = stiff = None
+    subsystems = schedules = splitting = conservative = curve = stiff = literal = None
     if not args.no_extras:
         stiff = run_stiff(R, torch, synth)
         log(f"stiffer mechanism: {stiff['ms']:.1f} ms, {stiff['attempts']} attempts, "
             f"{stiff['frac_fp64_peak'] * 100:.1f}% of FP64 peak")
+        literal = run_literal(R, torch, synth, fp64["tuning"])
+        log("literal draw: " + ", ".join(f"{k} {v['ms']:.1f} ms ({v['cells_per_s']:.3e} cells/s, "
+                                         f"{v['attempts_per_cell']['p50']:.0f} attempts/cell median, "
+                                         f"{v['frac_fp64_peak'] * 100:.1f}% of FP64 peak)"
+                                         for k, v in literal.items()))
         subsystems = run_subsystems(w, R, torch)
         log("subsystems: " + ", ".join(f"{k} {v['kernel_ms']:.3f} ms ({v['frac'] * 100:.1f}% of FP64 peak)"
                                        for k, v in subsystems.items()))
@@ -686,6 +740,8 @@ def main():
                         if (~same).any() else None}
     if stiff is not None:
         out["stiffer_mechanism"] = stiff
+    if literal is not None:
+        out["literal_draw"] = literal
     if subsystems is not None:
         out["subsystems"] = subsystems
     if schedules is not None:

@@ -277,23 +277,36 @@ int rok4e_tune(int64_t n_cells, rok4e_mech* mech, const double* Y, const double*
                void* stream);
 
 /* ---- Splitting around the reaction substep (Sec. 3.3) ------------------------------
- * Model transport operator on a periodic nx x ny x nz grid of cubic cells (cell
+ * Model transport operator on an nx x ny x nz grid of cubic cells (cell
  * c = x + nx (y + ny z), the cell index of the state arrays): advection with velocity vel
  * along x and diffusion with diffusivity diff, second-order central differences, applied
  * to every state row (mass fractions and temperature):
- *   T(U)_r = -vel (U_{x+1} - U_{x-1}) / (2 dx) + diff (sum of six neighbours - 6 U) / dx^2 */
+ *   T(U)_r = -vel (U_{x+1} - U_{x-1}) / (2 dx) + diff (sum of six neighbours - 6 U) / dx^2
+ * y and z are periodic.  Along x the grid is periodic, or open: the neighbour before x = 0
+ * is a ghost cell holding a fixed inflow state, the neighbour after x = nx - 1 repeats that
+ * cell (zero-gradient outflow).  An open grid has steady states that are not uniform (a
+ * premixed stream reacting as it flows through), the discrete steady states the balanced
+ * splitting is built to keep (definition d:steady_state_preserving). */
+#define ROK4E_X_PERIODIC 0
+#define ROK4E_X_INFLOW_OUTFLOW 1
+
 typedef struct {
   int32_t nx, ny, nz;
   double dx;     /* m, > 0 */
   double vel;    /* m/s */
   double diff;   /* m^2/s, >= 0 */
+  int32_t x_boundary;    /* ROK4E_X_PERIODIC or ROK4E_X_INFLOW_OUTFLOW */
+  const double* inflow;  /* INFLOW_OUTFLOW: device array [n_species + 1], the inflow ghost
+                            state (Y_1..Y_ns, T), owned by the caller and read by every call
+                            that takes the grid; PERIODIC: NULL */
 } rok4e_grid;
 
 #define ROK4E_SPLIT_SIMPLER 0  /* Simpler balanced splitting, e:simpler_balanced */
 #define ROK4E_SPLIT_STRANG 1   /* Strang splitting, e:strang_t1..e:strang_t3 (control) */
 
 /* S[r * n + c] = T(U)_r at cell c (n = nx ny nz) for the state (Y, T).  Device pointers;
- * EINVAL for a bad grid or null pointers. */
+ * EINVAL for a bad grid (sizes, dx, diff, an unknown x_boundary, an inflow pointer missing
+ * on an open grid or given on a periodic one) or null pointers. */
 int rok4e_transport(const rok4e_grid* g, int32_t n_species, const double* Y, const double* T, double* S,
                     void* stream);
 

@@ -66,13 +66,21 @@ def strang_step(T, R, u, h, reaction=rok4e, transport=rk4):
 
 # ---- grid form: the reaction substep per cell, the model transport operator on a grid ----
 
-def transport_grid(U, nx, ny, nz, dx, vel, diff):
-    """The model transport operator on a periodic nx x ny x nz grid (cell c = x + nx (y +
-    ny z)): advection with velocity vel along x and isotropic diffusion, second-order
-    central differences, for every row of U [N, n]."""
+def transport_grid(U, nx, ny, nz, dx, vel, diff, inflow=None):
+    """The model transport operator on an nx x ny x nz grid (cell c = x + nx (y + ny z)):
+    advection with velocity vel along x and isotropic diffusion, second-order central
+    differences, for every row of U [N, n].  y and z are periodic.  x is periodic when
+    inflow is None; otherwise the x-neighbour before the first cell is the ghost value
+    inflow[r] of row r and the x-neighbour after the last cell is that cell (zero-gradient
+    outflow)."""
     N = U.shape[0]
     V = U.reshape(N, nz, ny, nx)
-    xp, xm = np.roll(V, -1, axis=3), np.roll(V, 1, axis=3)
+    if inflow is None:
+        xp, xm = np.roll(V, -1, axis=3), np.roll(V, 1, axis=3)
+    else:
+        ghost = np.broadcast_to(np.asarray(inflow, np.float64).reshape(N, 1, 1, 1), (N, nz, ny, 1))
+        xm = np.concatenate([ghost, V[..., :-1]], axis=3)
+        xp = np.concatenate([V[..., 1:], V[..., -1:]], axis=3)
     yp, ym = np.roll(V, -1, axis=2), np.roll(V, 1, axis=2)
     zp, zm = np.roll(V, -1, axis=1), np.roll(V, 1, axis=1)
     adv = -vel * (xp - xm) / (2.0 * dx)
@@ -99,7 +107,8 @@ def simpler_step_grid(mech, Y, T, p, grid, h, rtol, atol, M, src=None, nsub=1, *
     """One Simpler balanced splitting step on the grid (e:simpler_balanced): c_n = -T(U_n);
     the reaction substep u' = R(u) + src - c_n over h, cell by cell with the oracle's
     ROK4E; the transport substep u' = T(u) + c_n over h/2.  grid = (nx, ny, nz, dx, vel,
-    diff).  Returns (Y, T, accepted, rejected, status)."""
+    diff) for a periodic grid, or with a seventh entry, the inflow ghost state, for a grid
+    open along x.  Returns (Y, T, accepted, rejected, status)."""
     U = _rows(Y, T)
     s0 = transport_grid(U, *grid)
     F = s0 if src is None else s0 + src

@@ -1312,12 +1312,16 @@ namespace {
 bool grid_ok(const rok4e_grid* g) {
   if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
   if ((int64_t)g->nx * g->ny * g->nz > INT32_MAX - 1) return false;
+  if (g->x_boundary == ROK4E_X_PERIODIC ? g->inflow != nullptr
+                                        : (g->x_boundary != ROK4E_X_INFLOW_OUTFLOW || !g->inflow))
+    return false;
   return g->dx > 0.0 && std::isfinite(g->dx) && std::isfinite(g->vel) && g->diff >= 0.0 &&
          std::isfinite(g->diff);
 }
 
 GridDev grid_dev(const rok4e_grid* g) {
-  return GridDev{g->nx, g->ny, g->nz, 0.5 / g->dx, 1.0 / (g->dx * g->dx), g->vel, g->diff};
+  return GridDev{g->nx, g->ny, g->nz, 0.5 / g->dx, 1.0 / (g->dx * g->dx), g->vel, g->diff,
+                 g->x_boundary == ROK4E_X_INFLOW_OUTFLOW ? g->inflow : nullptr};
 }
 
 int elementwise_grid(int64_t total) { return (int)std::min<int64_t>((total + 255) / 256, 65536); }

@@ -2,12 +2,14 @@
 // around the reaction substep).
 //
 // The transport operator of the model problem is linear advection along x plus isotropic
-// diffusion on a periodic nx x ny x nz grid of cubic cells:
+// diffusion on an nx x ny x nz grid of cubic cells:
 //   T(U)_r = -a (U_{x+1} - U_{x-1}) / (2 dx) + D (sum of the six neighbours - 6 U) / dx^2
 // for every state row r (species mass fractions and temperature), second-order central
-// differences.  Cell c = x + nx (y + ny z).  A state is addressed by rows: row r < ns is
-// y + r n, row ns is t (the ABI's Y / T arrays, or a contiguous [N][n] workspace with
-// t = y + ns n).
+// differences.  Cell c = x + nx (y + ny z).  y and z are periodic; x is periodic, or open:
+// the neighbour before x = 0 is the inflow ghost value of the row, the neighbour after
+// x = nx - 1 is that cell itself (zero-gradient outflow).  A state is addressed by rows:
+// row r < ns is y + r n, row ns is t (the ABI's Y / T arrays, or a contiguous [N][n]
+// workspace with t = y + ns n).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +21,7 @@ struct GridDev {
   int nx, ny, nz;
   double inv2dx, invdx2;   // 1 / (2 dx), 1 / dx^2
   double vel, diff;        // a, D
+  const double* inflow;    // open x boundary: ghost value per row; null: periodic x
 };
 
 struct RowsC {
@@ -36,15 +39,22 @@ struct RowsW {
   }
 };
 
-// T(U) at cell c of one row (periodic neighbours).
-__device__ __forceinline__ double transport_at(const GridDev& g, const double* u, int x, int y, int z) {
-  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+// T(U) at cell c of row r.
+__device__ __forceinline__ double transport_at(const GridDev& g, const double* u, int r, int x, int y, int z) {
   const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
   const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-  const int64_t c = x + sy * y + sz * z;
+  const int64_t line = sy * y + sz * z;
+  const int64_t c = x + line;
   const double uc = u[c];
-  const double uxm = u[xm + sy * y + sz * z], uxp = u[xp + sy * y + sz * z];
+  double uxm, uxp;
+  if (g.inflow) {
+    uxm = x == 0 ? g.inflow[r] : u[c - 1];
+    uxp = x == g.nx - 1 ? uc : u[c + 1];
+  } else {
+    uxm = u[(x == 0 ? g.nx - 1 : x - 1) + line];
+    uxp = u[(x == g.nx - 1 ? 0 : x + 1) + line];
+  }
   const double uym = u[x + sy * ym + sz * z], uyp = u[x + sy * yp + sz * z];
   const double uzm = u[x + sy * y + sz * zm], uzp = u[x + sy * y + sz * zp];
   const double adv = -g.vel * (uxp - uxm) * g.inv2dx;
@@ -62,7 +72,7 @@ __global__ void __launch_bounds__(256) k_transport(GridDev g, int ns, RowsC src,
     const int r = (int)(i / n);
     const int64_t c = i - (int64_t)r * n;
     const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((int64_t)g.nx * g.ny));
-    const double v = transport_at(g, src.row(r, ns, n), x, y, z);
+    const double v = transport_at(g, src.row(r, ns, n), r, x, y, z);
     out[i] = v;
     if (out2) out2[i] = add ? v + add[i] : v;
   }
@@ -80,7 +90,7 @@ __global__ void __launch_bounds__(256) k_rk4_stage(GridDev g, int ns, RowsC src,
     const int r = (int)(i / n);
     const int64_t c = i - (int64_t)r * n;
     const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((int64_t)g.nx * g.ny));
-    double k = transport_at(g, src.row(r, ns, n), x, y, z);
+    double k = transport_at(g, src.row(r, ns, n), r, x, y, z);
     if (s0) k = k - s0[i];
     const double b = base.row(r, ns, n)[c];
     const double a = (init ? b : acc[i]) + wacc * k;

@@ -58,9 +58,13 @@ class TuneResult(C.Structure):
                 ("candidates", C.c_int32), ("from_cache", C.c_int32)]
 
 
+X_PERIODIC, X_INFLOW_OUTFLOW = 0, 1
+
+
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dx", C.c_double),
-                ("vel", C.c_double), ("diff", C.c_double)]
+                ("vel", C.c_double), ("diff", C.c_double), ("x_boundary", C.c_int32),
+                ("inflow", C.c_void_p)]
 
 
 HIST_BINS = 22
@@ -119,8 +123,23 @@ def load():
     return _lib
 
 
-def grid(nx, ny, nz, dx, vel, diff) -> Grid:
-    return Grid(int(nx), int(ny), int(nz), float(dx), float(vel), float(diff))
+def grid(nx, ny, nz, dx, vel, diff, inflow=None) -> Grid:
+    """A periodic grid, or with inflow (a contiguous FP64 device tensor of ns + 1 values: the
+    ghost state before x = 0) an open one along x (zero-gradient outflow).  The grid keeps a
+    reference to the inflow tensor."""
+    if inflow is None:
+        return Grid(int(nx), int(ny), int(nz), float(dx), float(vel), float(diff), X_PERIODIC, None)
+    _need(inflow, inflow.numel(), "inflow")
+    g = Grid(int(nx), int(ny), int(nz), float(dx), float(vel), float(diff), X_INFLOW_OUTFLOW, _ptr(inflow))
+    g.inflow_tensor = inflow
+    return g
+
+
+def _need_inflow(g: Grid, n_species):
+    if g.x_boundary == X_INFLOW_OUTFLOW:
+        t = getattr(g, "inflow_tensor", None)
+        if t is not None and t.numel() != int(n_species) + 1:
+            raise ValueError(f"inflow: {t.numel()} values, expected n_species + 1 = {int(n_species) + 1}")
 
 
 def transport(g: Grid, n_species, Y, T, S, stream=None):
@@ -128,6 +147,7 @@ def transport(g: Grid, n_species, Y, T, S, stream=None):
     n = int(g.nx) * int(g.ny) * int(g.nz)
     for t, rows, name in ((Y, int(n_species), "Y"), (T, 1, "T"), (S, int(n_species) + 1, "S")):
         _need(t, rows * n, name, rows=rows)
+    _need_inflow(g, n_species)
     _check(load().rok4e_transport(C.byref(g), int(n_species), _ptr(Y), _ptr(T), _ptr(S), _stream(stream)),
            "rok4e_transport")
 
@@ -322,6 +342,7 @@ class Mech:
         ns = self.n_species
         for t, rows, name in ((Y, ns, "Y"), (T, 1, "T"), (p, 1, "p"), (src, ns + 1, "src")):
             _need(t, rows * n, name, rows=rows)
+        _need_inflow(grid, ns)
         _check(load().rok4e_split_step(self._h, C.byref(grid), int(scheme), _ptr(Y), _ptr(T), _ptr(p), _ptr(src),
                                        float(h), float(rtol), float(atol), int(nsub), _ptr(work),
                                        int(work.numel() * work.element_size()), _stream(stream)),

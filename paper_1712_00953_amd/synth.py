@@ -221,6 +221,16 @@ def states_flame(mech: Mechanism, nx: int, ny: int, seed: int) -> States:
     return States(np.ascontiguousarray(Y), T, np.full(nx * ny, P_ATM))
 
 
+def premixed_inflow(mech: Mechanism, seed: int, s: float = 0.5) -> np.ndarray:
+    """The inflow state (Y_1..Y_ns, T) of a premixed stream: the mixture of the flame
+    profile of ``states_flame`` (same seed) at progress s, Y = (1 - s) Y_u + s Y_b, at
+    T = 800 + 1400 s K, without the temperature noise."""
+    rng = np.random.default_rng(seed)
+    Y_u = rng.dirichlet(np.full(mech.n_species, 0.2))
+    Y_b = burnt_mixture(mech, Y_u)
+    return np.concatenate([(1.0 - s) * Y_u + s * Y_b, [800.0 + 1400.0 * s]])
+
+
 def states_bimodal(mech: Mechanism, n_cells: int, seed: int) -> States:
     """70 % cold cells (300-600 K, unburnt), 25 % burnt (1900-2300 K), 5 % flame front
     (1000-1600 K, s = (T - 800)/1400); cell order shuffled."""

@@ -68,3 +68,30 @@ def test_binding_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(R, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         R.load()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets the C compiler
+    gives the header's structs."""
+    import subprocess
+    from paper_1712_00953_amd import rok4e as R
+    structs = {"rok4e_mech_desc": R.MechDesc, "rok4e_options": R.Options, "rok4e_tune_result": R.TuneResult,
+               "rok4e_grid": R.Grid, "rok4e_stats": R.Stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rok4e.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        cname, field, value = line.split()
+        got[cname, field] = int(value)
+    for cname, py in structs.items():
+        assert got[cname, "size"] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[cname, fname] == getattr(py, fname).offset, (cname, fname)

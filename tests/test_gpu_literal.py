@@ -1,0 +1,79 @@
+"""GPU parity on the literal draw of the synthetic mechanism generator (pre-exponential
+factors log-uniform in [1e6, 1e14], no multiplier), through the C ABI.
+
+These cells take thousands to tens of thousands of ROK4E attempts over dt (1.5e3 to
+1.2e4 on the 9-species batch, 1.9e3 to 7.8e4 on the 53-species flame slice), so the
+result is the end of a long chain of accepted and rejected steps.  The checks are those
+of the other FP64 parity tests: relative error at most max(1e-10, 4x the oracle's FMA
+twin's) on every species above 1e-14 and on T, the tolerance-normalised difference
+within 4x the twin's (+1e-6), and accept/reject counts matching at the twin's rate up to
+binomial noise.  Over so many attempts rounding decides accept/reject at some step of
+most cells: the oracle and its twin take the same step sequence on only 31 % (9 species)
+and 47 % (53 species) of the cells and end up to 2.3 and 1.4 tolerance units apart, so
+on this draw the bar is the method's own rounding envelope, not 1e-10.  The GPU stays
+inside it (measured 2.2 and 1.2 tolerance units, count match 31 % and 47 %).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import envelope, gpu_integrate, normalized, parity, relative
+from paper_1712_00953_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+MAX_ATT = 1 << 22
+
+
+def match_floor(env_match, n):
+    """Lowest acceptable accept/reject count-match rate for an n-cell sample."""
+    return env_match - 3.0 * np.sqrt(max(env_match * (1 - env_match), 1e-4) / n) - 0.02
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1712_00953_amd import rok4e as R
+    R.load()
+    return R
+
+
+def _check(name, g, o, env, w):
+    mx, p99 = normalized(g, o, w.rtol, w.atol)
+    d = dict(norm_max=mx, norm_p99=p99, **env, **parity(g, o), rel=relative(g, o),
+             attempts_median=float(np.median(o[2] + o[3])), attempts_max=int((o[2] + o[3]).max()))
+    print(f"\n[{name}] " + " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}"
+                                     for k, v in d.items()), flush=True)
+    assert np.all(g[4] == 0) and np.all(o[4] == 0)
+    assert mx <= 4 * env["env_max"] + 1e-6
+    assert d["rel"] <= max(1e-10, 4 * env["env_rel"])
+    assert d["match_frac"] >= match_floor(env["env_match"], g[0].shape[1])
+
+
+def test_literal_draw_9_species_every_cell(R, orc):
+    w = synth.workload(1, a_scale=1.0)
+    st = w.states
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    o, env = envelope(orc, w, st, w.dt, w.rtol, w.atol, max_attempts=MAX_ATT)
+    _check("literal 9sp, 1,024 cells", g, o, env, w)
+    assert (o[2] + o[3]).min() > 1000
+    m.close()
+
+
+def test_literal_draw_53_species_full_batch_sampled(R, orc):
+    """The whole 65,536-cell flame slice in one launch; the oracle recomputes a stratified
+    sample of 32 cells."""
+    w = synth.workload(2, a_scale=1.0)
+    st = w.states
+    m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+    assert np.all(g[4] == 0)
+    idx = synth.stratified_sample(st.T, 32, 700)
+    sub = st.subset(idx)
+    o, env = envelope(orc, w, sub, w.dt, w.rtol, w.atol, max_attempts=MAX_ATT)
+    gs = (g[0][:, idx], g[1][idx], g[2][idx], g[3][idx], g[4][idx])
+    _check("literal 53sp, 32 of 65,536 cells", gs, o, env, w)
+    # whole batch: mass fractions keep their totals
+    assert np.abs(g[0].sum(0) - st.Y.sum(0)).max() <= 1e-9
+    m.close()

@@ -42,7 +42,8 @@ def _rel(Ya, Ta, Yb, Tb, floor=1e-14):
     return float(max(rY, (np.abs(Ta - Tb) / np.abs(Tb)).max()))
 
 
-def test_transport_operator_matches_oracle(R):
+@pytest.mark.parametrize("open_x", [False, True])
+def test_transport_operator_matches_oracle(R, open_x):
     import torch
     from oracle import splitting as SP
     nx, ny, nz = 24, 5, 3
@@ -51,25 +52,28 @@ def test_transport_operator_matches_oracle(R):
     ns = w.mech.n_species
     Y, T = _dev(st.Y, st.T)
     S = torch.zeros((ns + 1) * nx * ny * nz, dtype=torch.float64, device="cuda:0")
-    g = R.grid(nx, ny, nz, DX, VEL, DIFF)
+    inflow = synth.premixed_inflow(w.mech, 4100, s=0.2) if open_x else None
+    g = R.grid(nx, ny, nz, DX, VEL, DIFF, inflow=_dev(inflow)[0] if open_x else None)
     R.transport(g, ns, Y, T, S)
     torch.cuda.synchronize()
     U = np.vstack([st.Y, st.T[None, :]])
-    ref = SP.transport_grid(U, nx, ny, nz, DX, VEL, DIFF)
+    ref = SP.transport_grid(U, nx, ny, nz, DX, VEL, DIFF, inflow=inflow)
     got = S.cpu().numpy().reshape(ns + 1, -1)
     # each output is a sum of seven terms of size up to (|vel|/dx + 12 diff/dx^2) max|U_row|
     bound = (abs(VEL) / DX + 12 * DIFF / DX**2) * np.max(np.abs(U), axis=1, keepdims=True)
     assert np.max(np.abs(got - ref) / bound) <= 1e-14
 
 
-@pytest.mark.parametrize("scheme", ["simpler", "strang"])
-def test_split_step_parity(R, orc, scheme):
+@pytest.mark.parametrize("scheme,open_x", [("simpler", False), ("strang", False), ("simpler", True),
+                                           ("strang", True)])
+def test_split_step_parity(R, orc, scheme, open_x):
     import torch
     from oracle import splitting as SP
     nx, ny, nz = 16, 4, 4
     w = synth.workload(1, a_scale=A_SCALE, n_cells=4)
     st = synth.states_flame(w.mech, nx, ny * nz, 4200)
-    grid = (nx, ny, nz, DX, VEL, DIFF)
+    inflow = synth.premixed_inflow(w.mech, 4200, s=0.3) if open_x else None
+    grid = (nx, ny, nz, DX, VEL, DIFF) + ((inflow,) if open_x else ())
     h = 2e-7
     step = SP.simpler_step_grid if scheme == "simpler" else SP.strang_step_grid
     o = step(w.mech, st.Y, st.T, st.p, grid, h, w.rtol, w.atol, w.M, nsub=2)
@@ -77,7 +81,7 @@ def test_split_step_parity(R, orc, scheme):
     env = _norm(f[0], f[1], o[0], o[1], w.rtol, w.atol)
     env_rel = _rel(f[0], f[1], o[0], o[1])
     m = R.Mech(w.mech, M=w.M)
-    g = R.grid(*grid)
+    g = R.grid(nx, ny, nz, DX, VEL, DIFF, inflow=_dev(inflow)[0] if open_x else None)
     Y, T, p = _dev(st.Y, st.T, st.p)
     work = torch.empty(m.workspace_bytes(g) // 8, dtype=torch.float64, device="cuda:0")
     m.split_step(g, R.SPLIT_SIMPLER if scheme == "simpler" else R.SPLIT_STRANG, Y, T, p, h, w.rtol, w.atol,
@@ -86,7 +90,7 @@ def test_split_step_parity(R, orc, scheme):
     Yg, Tg = Y.cpu().numpy(), T.cpu().numpy()
     got = _norm(Yg, Tg, o[0], o[1], w.rtol, w.atol)
     rel = _rel(Yg, Tg, o[0], o[1])
-    print(f"\n[split {scheme}] rel={rel:.3e} (twin {env_rel:.3e}) norm_max={got:.3e} (twin {env:.3e})",
+    print(f"\n[split {scheme}{' open x' if open_x else ''}] rel={rel:.3e} (twin {env_rel:.3e}) norm_max={got:.3e} (twin {env:.3e})",
           flush=True)
     assert m.stats()["status_count"][0] == nx * ny * nz
     # the FP64 bar of the reaction substep: relative error at most max(1e-10, 4x the twin's)
@@ -171,6 +175,49 @@ def test_steady_state_on_the_full_grid(R):
     m.close()
 
 
+def test_steady_premixed_profile_on_the_full_grid(R):
+    """A premixed stream enters the 128^3 grid through the inflow ghost cell at x = 0 and
+    leaves through the zero-gradient outflow (y and z periodic), at 10 m/s, D = 2e-5 m^2/s,
+    dx = 1e-4 m, h = 5e-6 s (CFL 0.5).  Its discrete steady state, the profile along x on
+    which transport and reaction balance with no added source, comes from Newton's method
+    on the oracle (one x line; the state is uniform in y and z).  100 Simpler steps keep it
+    to 1e-8 relative (every species above 1e-14 relative to its own value, and T); two
+    Strang steps leave it."""
+    import torch
+    from oracle import steady as ST
+    nx = 128
+    n = nx ** 3
+    w = synth.workload(2, a_scale=A_SCALE, n_cells=4)
+    inflow = synth.premixed_inflow(w.mech, 4600)
+    Ux, steps, hist = ST.steady_premixed_line(w.mech, inflow, synth.P_ATM, nx, DX, VEL, DIFF, w.M)
+    print(f"\n[premixed 128^3] Newton steps {steps}, last relative step {hist[-1]:.2e}, T {Ux[-1, 0]:.2f} .. "
+          f"{Ux[-1, -1]:.2f} K", flush=True)
+    ns = w.mech.n_species
+    h = 0.5 * DX / VEL
+    U0 = torch.tensor(Ux, dtype=torch.float64, device="cuda:0").repeat(1, nx * nx)   # [ns + 1, n]
+    Y0, T0 = U0[:ns].contiguous(), U0[ns].contiguous()
+    del U0
+    p = torch.full((n,), synth.P_ATM, dtype=torch.float64, device="cuda:0")
+    g = R.grid(nx, nx, nx, DX, VEL, DIFF, inflow=_dev(inflow)[0])
+    m = R.Mech(w.mech, M=w.M)
+    work = torch.empty(m.workspace_bytes(g) // 8, dtype=torch.float64, device="cuda:0")
+    dev = {}
+    for name, scheme, nsteps in (("simpler", R.SPLIT_SIMPLER, 100), ("strang", R.SPLIT_STRANG, 2)):
+        Y, T = Y0.clone(), T0.clone()
+        for _ in range(nsteps):
+            m.split_step(g, scheme, Y, T, p, h, 1e-8, 1e-14, work)
+        torch.cuda.synchronize()
+        assert m.stats()["status_count"][0] == n
+        graded = torch.maximum(Y.abs(), Y0.abs()) >= 1e-14
+        relY = torch.where(graded, (Y - Y0).abs() / Y0.abs().clamp_min(1e-300), torch.zeros_like(Y))
+        dev[name] = float(torch.maximum(relY.amax(), ((T - T0).abs() / T0).amax()))
+        del graded, relY, Y, T
+        print(f"[premixed 128^3] {name}: {nsteps} steps, max deviation {dev[name]:.3e}", flush=True)
+    assert dev["simpler"] <= 1e-8
+    assert dev["strang"] >= 1e-6
+    m.close()
+
+
 def test_split_step_argument_errors(R):
     import torch
     w = synth.workload(1, a_scale=A_SCALE, n_cells=4)
@@ -186,4 +233,14 @@ def test_split_step_argument_errors(R):
         m.split_step(g, 7, Y, T, p, 1e-7, 1e-6, 1e-12, work)
     with pytest.raises(R.Rok4eError):
         m.split_step(R.grid(4, 2, 2, -1.0, VEL, DIFF), R.SPLIT_SIMPLER, Y, T, p, 1e-7, 1e-6, 1e-12, work)
+    # open grids: the inflow state has ns + 1 values; an unknown boundary, an open grid
+    # without an inflow state and a periodic one with it are refused by the library
+    inflow = torch.ones(w.mech.n_species + 1, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(ValueError):
+        m.split_step(R.grid(4, 2, 2, DX, VEL, DIFF, inflow=inflow[:-1]), R.SPLIT_SIMPLER, Y, T, p, 1e-7, 1e-6,
+                     1e-12, work)
+    for xb, ptr in ((2, inflow.data_ptr()), (R.X_INFLOW_OUTFLOW, None), (R.X_PERIODIC, inflow.data_ptr())):
+        bad = R.Grid(4, 2, 2, DX, VEL, DIFF, xb, ptr)
+        with pytest.raises(R.Rok4eError):
+            m.split_step(bad, R.SPLIT_SIMPLER, Y, T, p, 1e-7, 1e-6, 1e-12, work)
     m.close()
