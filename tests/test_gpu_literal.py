@@ -11,7 +11,10 @@ binomial noise.  Over so many attempts rounding decides accept/reject at some st
 most cells: the oracle and its twin take the same step sequence on only 31 % (9 species)
 and 47 % (53 species) of the cells and end up to 2.3 and 1.4 tolerance units apart, so
 on this draw the bar is the method's own rounding envelope, not 1e-10.  The GPU stays
-inside it (measured 2.2 and 1.2 tolerance units, count match 31 % and 47 %).
+inside it (measured 2.2 and 1.2 tolerance units, count match 31 % and 47 %).  The large
+relative spreads sit on species below 1e-8, whose error control is atol = 1e-12; on the
+species above 1e-8 and on T the twin's spread is ~2e-8, and the GPU is held to 4x the
+twin's spread on those entries as well.
 """
 import numpy as np
 import pytest
@@ -38,15 +41,19 @@ def R():
     return R
 
 
-def _check(name, g, o, env, w):
+def _check(name, g, o, env, w, twin):
     mx, p99 = normalized(g, o, w.rtol, w.atol)
     d = dict(norm_max=mx, norm_p99=p99, **env, **parity(g, o), rel=relative(g, o),
              attempts_median=float(np.median(o[2] + o[3])), attempts_max=int((o[2] + o[3]).max()))
+    # the species that the relative tolerance governs: above 1e-8 (the rounding spread of
+    # the species below it is set by atol = 1e-12, up to tens of percent of their value)
+    d.update(rel_above_1e8=relative(g, o, floor=1e-8), twin_rel_above_1e8=relative(twin, o, floor=1e-8))
     print(f"\n[{name}] " + " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}"
                                      for k, v in d.items()), flush=True)
     assert np.all(g[4] == 0) and np.all(o[4] == 0)
     assert mx <= 4 * env["env_max"] + 1e-6
     assert d["rel"] <= max(1e-10, 4 * env["env_rel"])
+    assert d["rel_above_1e8"] <= max(1e-10, 4 * d["twin_rel_above_1e8"])
     assert d["match_frac"] >= match_floor(env["env_match"], g[0].shape[1])
 
 
@@ -56,7 +63,8 @@ def test_literal_draw_9_species_every_cell(R, orc):
     m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
     g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
     o, env = envelope(orc, w, st, w.dt, w.rtol, w.atol, max_attempts=MAX_ATT)
-    _check("literal 9sp, 1,024 cells", g, o, env, w)
+    twin = orc.integrate(w.mech, st.Y, st.T, st.p, w.dt, w.rtol, w.atol, w.M, max_attempts=MAX_ATT, fma=True)
+    _check("literal 9sp, 1,024 cells", g, o, env, w, twin)
     assert (o[2] + o[3]).min() > 1000
     m.close()
 
@@ -72,8 +80,9 @@ def test_literal_draw_53_species_full_batch_sampled(R, orc):
     idx = synth.stratified_sample(st.T, 32, 700)
     sub = st.subset(idx)
     o, env = envelope(orc, w, sub, w.dt, w.rtol, w.atol, max_attempts=MAX_ATT)
+    twin = orc.integrate(w.mech, sub.Y, sub.T, sub.p, w.dt, w.rtol, w.atol, w.M, max_attempts=MAX_ATT, fma=True)
     gs = (g[0][:, idx], g[1][idx], g[2][idx], g[3][idx], g[4][idx])
-    _check("literal 53sp, 32 of 65,536 cells", gs, o, env, w)
+    _check("literal 53sp, 32 of 65,536 cells", gs, o, env, w, twin)
     # whole batch: mass fractions keep their totals
     assert np.abs(g[0].sum(0) - st.Y.sum(0)).max() <= 1e-9
     m.close()
