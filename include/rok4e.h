@@ -104,6 +104,12 @@ typedef struct {
   const double* lnAr;         /* [nr] reverse triple, same meaning */
   const double* br;
   const double* Er;
+  int32_t n_elements;         /* E >= 0; 0: no element table (no balance check) */
+  const int8_t* elem;         /* [ns * E] atoms of element e in species k at k*E + e, or NULL
+                                 when E = 0.  rok4e_mech_create refuses (EINVAL) a mechanism
+                                 in which a reaction changes the count of any element: the
+                                 mass-action source then conserves elements and, with
+                                 element-consistent weights, mass (Sec. 4.4) */
 } rok4e_mech_desc;
 
 typedef struct {

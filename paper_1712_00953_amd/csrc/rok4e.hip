@@ -928,6 +928,18 @@ int rok4e_mech_create(const rok4e_mech_desc* d, const rok4e_options* o, rok4e_me
     }
     if (d->reac[2 * j] < 0 || d->prod[2 * j] < 0) return ROK4E_EINVAL;   // first slot filled
   }
+  // element balance of every reaction, when the caller gives the element table
+  if (d->n_elements < 0 || (d->n_elements > 0 && !d->elem)) return ROK4E_EINVAL;
+  for (int j = 0; j < nr && d->n_elements > 0; ++j)
+    for (int e = 0; e < d->n_elements; ++e) {
+      int net = 0;
+      for (int a = 0; a < 2; ++a) {
+        const int r = d->reac[2 * j + a], q = d->prod[2 * j + a];
+        if (r >= 0) net += d->elem[(size_t)r * d->n_elements + e];
+        if (q >= 0) net -= d->elem[(size_t)q * d->n_elements + e];
+      }
+      if (net != 0) return ROK4E_EINVAL;
+    }
   if (ns > 254) return ROK4E_ENOTSUP;
   const Variant* var = pick_variant(ns, opt);
   if (!var) return ROK4E_ENOTSUP;

@@ -40,7 +40,8 @@ class MechDesc(C.Structure):
                 ("W", C.c_void_p), ("cp", C.c_void_p), ("hf", C.c_void_p),
                 ("reac", C.c_void_p), ("prod", C.c_void_p),
                 ("lnAf", C.c_void_p), ("bf", C.c_void_p), ("Ef", C.c_void_p),
-                ("lnAr", C.c_void_p), ("br", C.c_void_p), ("Er", C.c_void_p)]
+                ("lnAr", C.c_void_p), ("br", C.c_void_p), ("Er", C.c_void_p),
+                ("n_elements", C.c_int32), ("elem", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -223,7 +224,11 @@ class Mech:
             np.asarray(mech.lnAr, np.float64), np.asarray(mech.br, np.float64), np.asarray(mech.Er, np.float64))]
         self.n_species = int(mech.n_species)
         self.n_reactions = int(mech.n_reactions)
-        desc = MechDesc(self.n_species, self.n_reactions, *[a.ctypes.data for a in self._arrays])
+        elem = getattr(mech, "elem", None)
+        self._elem = None if elem is None else np.ascontiguousarray(np.asarray(elem, np.int8))
+        n_el = 0 if self._elem is None else int(self._elem.shape[1])
+        desc = MechDesc(self.n_species, self.n_reactions, *[a.ctypes.data for a in self._arrays],
+                        n_el, None if self._elem is None else self._elem.ctypes.data)
         self.opts = opts if opts is not None else options(**kw)
         h = C.c_void_p()
         _check(lib.rok4e_mech_create(C.byref(desc), C.byref(self.opts), C.byref(h)), "rok4e_mech_create")

@@ -62,6 +62,24 @@ def test_argument_errors_before_any_device_work(lib):
     assert lib.rok4e_get_stats(None, C.byref(s), None) == R.EINVAL
 
 
+def test_mechanism_with_an_unbalanced_reaction_is_refused(lib):
+    """A <=> B where A holds one atom of the element and B two: refused on the host, before
+    any device work; so is an element count without its table."""
+    import numpy as np
+    from paper_1712_00953_amd import rok4e as R
+    W, cp, hf = np.array([0.001, 0.002]), np.array([1000.0, 1000.0]), np.zeros(2)
+    reac, prod = np.array([0, -1], np.int32), np.array([1, -1], np.int32)
+    par = [np.zeros(1) for _ in range(6)]
+    elem = np.array([[1], [2]], np.int8)
+    arrays = [W, cp, hf, reac, prod, *par]
+    for n_el, table in ((1, elem), (1, None)):
+        d = R.MechDesc(2, 1, *[a.ctypes.data for a in arrays], n_el,
+                       None if table is None else table.ctypes.data)
+        h = C.c_void_p()
+        assert lib.rok4e_mech_create(C.byref(d), None, C.byref(h)) == R.EINVAL
+        assert not h.value
+
+
 def test_binding_has_no_fallback(monkeypatch, tmp_path):
     from paper_1712_00953_amd import rok4e as R
     monkeypatch.setattr(R, "LIB_PATH", str(tmp_path / "missing.so"))
