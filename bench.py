@@ -258,6 +258,28 @@ def run_literal(R, torch, synth, tuning=None):
     return out
 
 
+def run_peak_check(R, torch, reps=5):
+    """The attainable FP64 vector FMA rate (rok4e_fma_probe: eight independent FMA chains
+    per thread, 2,048 blocks of 256) and HBM copy bandwidth (a 4 GiB device copy: 4 GiB
+    read, 4 GiB written), medians of reps runs, beside the datasheet peaks the roofline
+    fractions use."""
+    stream = torch.cuda.current_stream()
+    n, iters = 2048 * 256, 8192
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    R.fma_probe(out, 64)
+    t_fma = float(np.median(timed_events(torch, stream, lambda: R.fma_probe(out, iters), reps)))
+    x = torch.ones(512 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    t_copy = float(np.median(timed_events(torch, stream, lambda: y.copy_(x), reps)))
+    nbytes = 2 * x.numel() * 8
+    del x, y, out
+    torch.cuda.empty_cache()
+    return {"fp64_fma_tflops": 16.0 * n * iters / t_fma * 1e-12, "fp64_datasheet_tflops": PEAK_FP64_TFLOPS,
+            "hbm_copy_gbps": nbytes / t_copy * 1e-9, "hbm_datasheet_gbps": 8000.0,
+            "note": "roofline fractions use the datasheet peaks"}
+
+
 def run_subsystems(w, R, torch, reps=5):
     """The right-hand side and the Arnoldi basis (f(u_n), M JVPs, Gram-Schmidt) as
     standalone kernels over the same batch, against the FP64 vector peak."""
@@ -545,6 +567,14 @@ def run_cpu_baseline(w, target_s=10.0):
     rec = dict(value=n / el, unit="cell-integrations/s", cores=threads, kind="oracle",
                sample=f"{n} cells drawn uniformly (seed 78) from the {st.n_cells}-cell batch, "
                       f"{el:.1f} s wall on {threads} threads of {cpu_model()}")
+    # one thread on an equal share of the sample: the per-core rate
+    n1 = max(16, n // threads)
+    sub1 = st.subset(idx[:n1])
+    t0 = time.perf_counter()
+    O.integrate(w.mech, sub1.Y, sub1.T, sub1.p, w.dt, w.rtol, w.atol, w.M, nthreads=1)
+    el1 = time.perf_counter() - t0
+    rec["single_thread"] = {"value": n1 / el1, "unit": "cell-integrations/s", "cores": 1,
+                            "sample": f"the first {n1} cells of that sample, {el1:.1f} s wall"}
     return rec, (idx, *res)
 
 
@@ -626,7 +656,7 @@ def main():
         mixed = run_gpu(w, R.MIXED, args.steps, args.warmup, R, torch, tune=not args.no_tune,
                         graph_reps=0, layout=layout)
         log(f"mixed: {mixed['cells_per_s']:.4e} cells/s, {mixed['ms_per_step']:.2f} ms/step")
-    subsystems = schedules = splitting = conservative = curve = stiff = literal = None
+    subsystems = schedules = splitting = conservative = curve = stiff = literal = peaks = None
     if not args.no_extras:
         stiff = run_stiff(R, torch, synth)
         log(f"stiffer mechanism: {stiff['ms']:.1f} ms, {stiff['attempts']} attempts, "
@@ -636,6 +666,9 @@ def main():
                                          f"{v['attempts_per_cell']['p50']:.0f} attempts/cell median, "
                                          f"{v['frac_fp64_peak'] * 100:.1f}% of FP64 peak)"
                                          for k, v in literal.items()))
+        peaks = run_peak_check(R, torch)
+        log(f"peak check: FP64 FMA {peaks['fp64_fma_tflops']:.1f} TFLOP/s (datasheet "
+            f"{PEAK_FP64_TFLOPS}), HBM copy {peaks['hbm_copy_gbps']:.0f} GB/s (datasheet 8000)")
         subsystems = run_subsystems(w, R, torch)
         log("subsystems: " + ", ".join(f"{k} {v['kernel_ms']:.3f} ms ({v['frac'] * 100:.1f}% of FP64 peak)"
                                        for k, v in subsystems.items()))
@@ -744,6 +777,8 @@ def main():
         out["literal_draw"] = literal
     if subsystems is not None:
         out["subsystems"] = subsystems
+    if peaks is not None:
+        out["peak_check"] = peaks
     if schedules is not None:
         out["schedules"] = schedules
     if splitting is not None:

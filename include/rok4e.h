@@ -345,6 +345,13 @@ int rok4e_rhs(int64_t n_cells, rok4e_mech* mech, const double* Y, const double* 
 int rok4e_arnoldi(int64_t n_cells, rok4e_mech* mech, const double* Y, const double* T,
                   const double* p, double* Q, double* H, int32_t* Meff, void* stream);
 
+/* Diagnostic, not part of the method: the attainable FP64 vector FMA rate, the compute
+ * roofline the integration kernel is measured against.  n_threads threads (a multiple of
+ * 256) each run iters rounds of eight independent fused multiply-add chains and store
+ * their sum in out[thread] (device, [n_threads], owned by the caller): 16 * n_threads *
+ * iters FP64 operations.  EINVAL for a bad size or a null out. */
+int rok4e_fma_probe(int64_t n_threads, int32_t iters, double* out, void* stream);
+
 /* Copies the summary of the last integrate call to the host (synchronises stream). */
 int rok4e_get_stats(rok4e_mech* m, rok4e_stats* out, void* stream);
 

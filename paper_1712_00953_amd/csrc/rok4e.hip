@@ -23,6 +23,20 @@ namespace rok4e {
 
 __global__ void k_zero_u32(unsigned int* x) { *x = 0u; }
 
+// FP64 FMA throughput probe: eight independent chains per thread (enough to cover the
+// FMA latency with a few waves per SIMD), each round eight FMAs.
+__global__ void __launch_bounds__(256) k_fma_probe(int iters, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double b = 0.9999999999, c = 1e-12 * (double)(threadIdx.x + 1);
+  double a[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a[q] = 1.0 + 0.125 * q;
+  for (int it = 0; it < iters; ++it)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = fma(a[q], b, c);
+  out[i] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 // ---------------------------------------------------------- cell order ----
 // Hottest-first order of the persistent queue: a counting sort of the cells by
 // temperature bin (16 K wide, bin 0 the hottest; non-finite or non-positive T in the
@@ -1282,6 +1296,14 @@ int rok4e_tune(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T,
   res.candidates = (int32_t)cand.size();
   if (out) *out = res;
   return ROK4E_OK;
+}
+
+int rok4e_fma_probe(int64_t n_threads, int32_t iters, double* out, void* stream) {
+  if (n_threads < 256 || n_threads % 256 || n_threads / 256 > INT32_MAX || iters < 1 || !out)
+    return ROK4E_EINVAL;
+  hipLaunchKernelGGL(k_fma_probe, dim3((unsigned)(n_threads / 256)), dim3(256), 0, (hipStream_t)stream, iters, out);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ROK4E_OK : hip_fail(e);
 }
 
 int rok4e_rhs(int64_t n_cells, rok4e_mech* m, const double* Y, const double* T, const double* p,

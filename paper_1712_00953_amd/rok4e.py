@@ -32,7 +32,7 @@ EXPORTS = ["rok4e_options_default", "rok4e_mech_create", "rok4e_mech_destroy", "
            "rok4e_integrate_ex", "rok4e_integrate_conservative", "rok4e_integrate_static",
            "rok4e_tune", "rok4e_rhs", "rok4e_arnoldi", "rok4e_transport", "rok4e_split_workspace_bytes",
            "rok4e_split_step", "rok4e_get_stats", "rok4e_cell_stats_ptr",
-           "rok4e_copy_cell_stats", "rok4e_strerror"]
+           "rok4e_copy_cell_stats", "rok4e_fma_probe", "rok4e_strerror"]
 
 
 class MechDesc(C.Structure):
@@ -109,6 +109,7 @@ def load():
         lib.rok4e_integrate_ex.argtypes = [i64, vp, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_conservative.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, vp]
         lib.rok4e_integrate_static.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp]
+        lib.rok4e_fma_probe.argtypes = [i64, C.c_int32, vp, vp]
         lib.rok4e_tune.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, C.c_int32, C.POINTER(TuneResult), vp]
         lib.rok4e_rhs.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
         lib.rok4e_transport.argtypes = [C.POINTER(Grid), C.c_int32, vp, vp, vp, vp]
@@ -151,6 +152,13 @@ def transport(g: Grid, n_species, Y, T, S, stream=None):
     _need_inflow(g, n_species)
     _check(load().rok4e_transport(C.byref(g), int(n_species), _ptr(Y), _ptr(T), _ptr(S), _stream(stream)),
            "rok4e_transport")
+
+
+def fma_probe(out, iters, stream=None):
+    """rok4e_fma_probe: out.numel() threads (a multiple of 256) each run iters rounds of
+    eight FP64 FMA chains; 16 * out.numel() * iters operations."""
+    _need(out, out.numel(), "out")
+    _check(load().rok4e_fma_probe(int(out.numel()), int(iters), _ptr(out), _stream(stream)), "rok4e_fma_probe")
 
 
 def strerror(code: int) -> str:
