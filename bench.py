@@ -742,6 +742,13 @@ def main():
         out["roofline"]["traffic_detail"] = {k: traffic[k] for k in (
             "fetch_bytes_per_launch", "write_bytes_per_launch", "copy_scale_fetch", "copy_scale_write",
             "profile")}
+        if "executed_fp64_ops_per_launch" in traffic:
+            # FP64 operations the hardware executed (counters, every lane, FMA as two) over
+            # the same launch time: the work the kernel issues, against the algorithmic work
+            ex = traffic["executed_fp64_ops_per_launch"] / fp64["kernel_s"] * 1e-12
+            out["roofline"]["executed"] = {"tflops": ex, "frac": ex / PEAK_FP64_TFLOPS,
+                                           "issued_over_algorithmic": ex / achieved,
+                                           "profile": traffic.get("counters_profile")}
     if mixed is not None:
         # error of the mixed result against the FP64 result of the same batch (every cell;
         # species above 1e-14 and T)
