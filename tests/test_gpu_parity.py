@@ -572,11 +572,16 @@ def test_forcing_cancelling_f_is_identity(R, orc, cfg):
 
 @pytest.mark.parametrize("cfg,n_check", [(2, 4096), (3, 1024), (4, 256)])
 def test_full_batch_sampled(R, orc, cfg, n_check):
-    """The full batch in the benchmark's launch configuration; the oracle recomputes a
-    seeded sample of cells one by one."""
+    """The full batch in the benchmark's launch configuration (the launch tuner runs on the
+    batch first, as bench.py does); the oracle recomputes a seeded sample of cells one by
+    one."""
     w = synth.workload(cfg, a_scale=A_SCALE)
     st = w.states
     m = R.Mech(w.mech, M=w.M, max_attempts=MAX_ATT)
+    Yd, Td, pd = dev_state(st)
+    tuned = m.tune(Yd, Td, pd, w.dt, w.rtol, w.atol)
+    del Yd, Td, pd
+    print(f"\n[full cfg{cfg}] tuned layout {tuned}", flush=True)
     g = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
     assert np.all(g[4] == 0)
     idx = synth.stratified_sample(st.T, n_check, 300 + cfg)
