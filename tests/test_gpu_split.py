@@ -64,6 +64,33 @@ def test_transport_operator_matches_oracle(R, open_x):
     assert np.max(np.abs(got - ref) / bound) <= 1e-14
 
 
+@pytest.mark.parametrize("dims,open_x", [((1, 3, 2), True), ((1, 3, 2), False), ((2, 1, 1), True),
+                                         ((5, 1, 7), True)])
+def test_transport_on_degenerate_grids(R, dims, open_x):
+    """Grids one or two cells wide along an axis: the neighbours of a periodic axis of
+    length one are the cell itself, an open x line of one cell has the inflow ghost on one
+    side and itself on the other."""
+    import torch
+    from oracle import splitting as SP
+    nx, ny, nz = dims
+    w = synth.workload(1, a_scale=A_SCALE, n_cells=4)
+    st = synth.states_flame(w.mech, nx, ny * nz, 4150)
+    ns = w.mech.n_species
+    Y, T = _dev(st.Y, st.T)
+    S = torch.zeros((ns + 1) * nx * ny * nz, dtype=torch.float64, device="cuda:0")
+    inflow = synth.premixed_inflow(w.mech, 4150, s=0.7) if open_x else None
+    g = R.grid(nx, ny, nz, DX, VEL, DIFF, inflow=_dev(inflow)[0] if open_x else None)
+    R.transport(g, ns, Y, T, S)
+    torch.cuda.synchronize()
+    U = np.vstack([st.Y, st.T[None, :]])
+    ref = SP.transport_grid(U, nx, ny, nz, DX, VEL, DIFF, inflow=inflow)
+    got = S.cpu().numpy().reshape(ns + 1, -1)
+    scale = np.maximum(np.max(np.abs(U), axis=1, keepdims=True),
+                       np.abs(inflow)[:, None] if open_x else 0.0)
+    bound = (abs(VEL) / DX + 12 * DIFF / DX**2) * scale
+    assert np.max(np.abs(got - ref) / bound) <= 1e-14
+
+
 @pytest.mark.parametrize("scheme,open_x", [("simpler", False), ("strang", False), ("simpler", True),
                                            ("strang", True)])
 def test_split_step_parity(R, orc, scheme, open_x):
