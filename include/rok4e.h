@@ -130,10 +130,12 @@ typedef struct {
                              neutral; persistent schedule) */
   int32_t jvp_gather;     /* ROK4E_GATHER_AUTO (default), _LDS or _PRIVATE (bitwise neutral;
                              persistent schedule) */
-  int32_t waves_per_simd; /* 0 (automatic: 3 for one-slot layouts, 2 for others) or 4: the
-                             persistent ROK4E kernel compiled for four waves per SIMD (64-lane
-                             one-slot layouts with M <= 8, LDS reads; blocks of up to 16
-                             waves; bitwise neutral) */
+  int32_t waves_per_simd; /* 4: the persistent ROK4E kernel compiled for four waves per SIMD
+                             (64-lane one-slot layouts with M <= 8, LDS reads; blocks of up to
+                             16 waves); 3: three waves for one-slot layouts (two for others);
+                             0 (automatic): the four-wave build for FP64 when the layout has
+                             it, waves_per_block and blocks_per_cu are automatic and the JVP
+                             gather is not private, else as 3.  Bitwise neutral */
   double h0;              /* first trial step; <= 0 means dt */
 } rok4e_options;
 
