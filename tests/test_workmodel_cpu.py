@@ -1,8 +1,8 @@
 """The algorithmic work model behind the roofline (paper_1712_00953_amd/workmodel.py).
 
 Pins: the per-unit figures the benchmark's roofline is built from (53 species, 325
-reactions, M = 8), the survey-level estimate of one right-hand side (about 21 R + 13 N_S
-operations plus 2 R exponentials), the launch total of the benchmark batch (6,045,553
+reactions, M = 8), a rough count of one right-hand side (about 21 R + 13 N_S operations
+plus 2 R exponentials), the launch total of the benchmark batch (6,045,553
 new-basis attempts and 164,308 retries give 7.40e11 operations), the cell-state bytes
 (872 per cell at 53 species), and the monotone growth of an attempt with M.
 """
