@@ -87,3 +87,27 @@ def test_literal_draw_53_species_full_batch_sampled(R, orc):
     # whole batch: mass fractions keep their totals
     assert np.abs(g[0].sum(0) - st.Y.sum(0)).max() <= 1e-9
     m.close()
+
+
+@pytest.mark.parametrize("cfg,n", [(1, None), (2, 2048)])
+def test_literal_draw_mixed_form_stays_within_tolerance_units(R, cfg, n):
+    """The mixed FP32/FP64 form on the literal draw, against the FP64 GPU result of the same
+    cells.  Over thousands of attempts FP32 rates of progress change the step sequence of
+    every cell, so the two runs are different solutions of the same tolerance: the check is
+    that every cell finishes and that the results agree to a few tolerance units (measured
+    1.9 on the 9-species batch, 7.1 at most and 1.4 at the 99th percentile on the 53-species
+    sample; relative 1.5e-6 and 4.1e-4 on species above 1e-8).  The 1e-5 relative bar of the
+    mixed form holds on the calibrated workloads (test_gpu_parity.py), not here."""
+    w = synth.workload(cfg, a_scale=1.0)
+    st = w.states if n is None else w.states.subset(synth.stratified_sample(w.states.T, n, 5))
+    res = {}
+    for prec in (R.FP64, R.MIXED):
+        m = R.Mech(w.mech, M=w.M, precision=prec, max_attempts=MAX_ATT)
+        res[prec] = gpu_integrate(m, st, w.dt, w.rtol, w.atol)
+        m.close()
+    a, b = res[R.FP64], res[R.MIXED]
+    mx, p99 = normalized(b, a, w.rtol, w.atol)
+    print(f"\n[literal mixed cfg{cfg}] normalized max {mx:.3e} p99 {p99:.3e} relative above 1e-8 "
+          f"{relative(b, a, floor=1e-8):.3e}", flush=True)
+    assert np.all(b[4] == 0) and np.all(a[4] == 0)
+    assert mx <= 20.0 and p99 <= 3.0
