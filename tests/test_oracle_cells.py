@@ -42,6 +42,23 @@ def test_conservation_complex_step(orc, cfg, n):
     assert np.max(np.abs(T - st.T)) > 1.0          # the cells do react
 
 
+def test_conservation_over_thousands_of_steps_on_the_literal_draw(orc):
+    # the generator without the pre-exponential multiplier: 1.5e3 to 1.2e4 attempts per
+    # cell over dt; with exact Jacobian-vector products mass and elements still hold to
+    # roundoff accumulated over that many steps
+    w = synth.workload(1, a_scale=1.0)
+    idx = synth.stratified_sample(w.states.T, 32, 13)
+    st = w.states.subset(idx)
+    Y, T, acc, rej, s = orc.integrate(w.mech, st.Y, st.T, st.p, w.dt, w.rtol, w.atol, w.M,
+                                      jvp=orc.JVP_COMPLEX, max_attempts=1 << 22)
+    assert np.all(s == 0)
+    assert np.min(acc + rej) > 1000
+    assert np.max(np.abs(Y.sum(0) - st.Y.sum(0))) <= 1e-12
+    e0 = synth.element_moles(w.mech, st.Y)
+    e1 = synth.element_moles(w.mech, Y)
+    assert np.max(np.abs(e1 - e0) / np.abs(e0)) <= 1e-12
+
+
 def test_conservation_finite_difference(orc):
     # FD Jacobian-vector products carry roundoff eps*|f|/delta into the Krylov basis,
     # so the invariants drift by ~1e-12 over ~75 steps instead of ~1e-16.
