@@ -547,13 +547,22 @@ __device__ __forceinline__ void rhs(const DevMech& m, const MechLds& t, const do
   char* rb = (char*)S.spc;
   char* ab = acc_base<LP, RT>(rb, lane);
   lds_sync();
+  // species offsets one iteration ahead where the registers allow (as in rhs_diff)
+  constexpr bool kPrefetch = !(L == 64 && ROWS == 1);
+  uint2 on = t.rxo[lane < m.nr ? lane : 0];
 #pragma unroll ROK4E_RX_UNROLL
   for (int j = lane; j < m.nr; j += L) {
     const double2 lnA = t.lnA[j], bEf = t.bEf[j], bEr = t.bEr[j];
     const RT kf = arrhenius(lnA.x, bEf.x, bEf.y, lnT, invRT, RT(0));
     const RT kr = arrhenius(lnA.y, bEr.x, bEr.y, lnT, invRT, RT(0));
     if constexpr (SAVE) S.k[j] = {kf, kr};
-    const uint2 o = t.rxo[j];
+    uint2 o;
+    if constexpr (kPrefetch) {
+      o = on;
+      on = t.rxo[min(j + L, m.nr - 1)];
+    } else {
+      o = t.rxo[j];
+    }
     const RT pf = *(const RT*)(rb + (o.x & 0xFFFFu)) * *(const RT*)(rb + (o.x >> 16));
     const RT pr = *(const RT*)(rb + (o.y & 0xFFFFu)) * *(const RT*)(rb + (o.y >> 16));
     scatter_rate<LP, RT>(ab, o, kf * pf - kr * pr);
@@ -684,9 +693,20 @@ __device__ __forceinline__ void rhs_diff(const DevMech& m, const MechLds& t, con
     }
   }
   if (NIT == 0 || !cc) {
+    // the next reaction's species offsets are loaded one iteration ahead in the layouts
+    // with room for the two registers (measured 1-2 % faster there; the one-slot 64-lane
+    // layouts spill them)
+    constexpr bool kPrefetch = !(L == 64 && ROWS == 1);
+    uint2 on = t.rxo[lane < m.nr ? lane : 0];
 #pragma unroll ROK4E_RX_UNROLL
     for (int j = lane; j < m.nr; j += L) {
-      const uint2 o = t.rxo[j];
+      uint2 o;
+      if constexpr (kPrefetch) {
+        o = on;
+        on = t.rxo[min(j + L, m.nr - 1)];
+      } else {
+        o = t.rxo[j];
+      }
       diff_rx(j, o, *(const RT*)(rb + (o.x & 0xFFFFu)), *(const RT*)(rb + (o.x >> 16)),
               *(const RT*)(rb + (o.y & 0xFFFFu)), *(const RT*)(rb + (o.y >> 16)));
     }
